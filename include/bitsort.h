@@ -1,0 +1,180 @@
+/*
+ * bitsort.h -- C ABI of the MI355X (gfx950) bitmap sort library, libbitsort.so.
+ *
+ * The operation (Yordzhev, "The bitwise operations related to a fast sorting
+ * algorithm", arXiv:1312.0138): sort an integer array ascending (Section IV,
+ * Section V, Theorem 1), here for distinct unsigned keys bounded by
+ * R = 2^range_bits.  Each key is marked as one bit of a bit-vector (shift and
+ * OR: Section II Table I, Section III Examples 2 and 3); the words are then
+ * scanned in order, set bits counted (Example 6), and the positions of the
+ * set bits written out (Example 1; bit 0 is the rightmost, Section II).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Key and output pointers are DEVICE pointers (hipMalloc'ed or a torch
+ *   tensor's data pointer).  The caller owns them; the library never frees
+ *   them.  Unless stated otherwise, offsets / range_bits arrays are device
+ *   pointers too.
+ * - `stream` is a hipStream_t passed as an opaque pointer; NULL means the
+ *   default stream.  Every call only enqueues work on `stream` and returns;
+ *   nothing is synchronised except where a function says so.
+ * - Return value: BITSORT_OK or a BITSORT_ERR_* code, decided on the host
+ *   before anything is enqueued (argument checks) or from a failed HIP call.
+ * - Data errors found on the device (a key >= R, a duplicate key) are not
+ *   return codes: they set BITSORT_STATUS_* flags that bitsort_get_status()
+ *   reads after the work has finished.  No such key causes a write outside
+ *   the output array.
+ * - A key >= R is dropped.  With duplicates each distinct key is written
+ *   once.  In both cases out[0 .. d) holds the d distinct in-range keys in
+ *   ascending order, and d is reported as bitsort_status_t.count.  Slots
+ *   out[d .. n) are left untouched when only out-of-range keys occurred; after
+ *   a duplicate their content is unspecified.
+ * - Thread safety: calls on different streams may run concurrently; calls on
+ *   one stream are ordered by that stream.
+ */
+#ifndef BITSORT_H
+#define BITSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *bitsort_stream_t; /* a hipStream_t */
+
+/* Return codes. */
+#define BITSORT_OK 0
+#define BITSORT_ERR_INVALID_ARG 1 /* null pointer with n > 0, range_bits > 32, partial overlap, ... */
+#define BITSORT_ERR_TOO_LARGE 2   /* n > 2^range_bits, n >= 2^32, or beyond a stated limit */
+#define BITSORT_ERR_NO_MEMORY 3   /* workspace allocation failed, or a caller workspace is too small */
+#define BITSORT_ERR_HIP 4         /* a HIP runtime call or kernel launch failed */
+
+/* Device status flags (bitsort_status_t.flags). */
+#define BITSORT_STATUS_OUT_OF_RANGE 1u /* some key was >= 2^range_bits and was dropped */
+#define BITSORT_STATUS_DUPLICATE 2u    /* some key occurred more than once */
+
+typedef struct bitsort_status {
+    uint32_t flags;  /* BITSORT_STATUS_* bits */
+    uint32_t _pad;
+    uint64_t count;  /* d: number of keys written (distinct, in range) */
+} bitsort_status_t;
+
+/* Library version, e.g. 10000 for 1.0.0. */
+int bitsort_version(void);
+
+/* Human-readable text for a return code (static storage). */
+const char *bitsort_error_string(int code);
+
+/*
+ * Sort n distinct uint32 keys, each < 2^range_bits, ascending into out.
+ *   keys        device, n elements, read only.
+ *   n           number of keys, n < 2^32 and n <= 2^range_bits.
+ *   range_bits  0..32; the key range is [0, 2^range_bits).
+ *   out         device, n elements.  out == keys (exact alias, in-place
+ *               sort) is allowed; any other overlap is BITSORT_ERR_INVALID_ARG.
+ *   stream      see above.
+ * Uses a workspace the library allocates on first use per (device, stream)
+ * and keeps, growing it when a larger problem comes (about 4n bytes plus a
+ * small table).  n = 0 enqueues nothing.
+ * Method: Sections II-III (mark with shift/OR), Example 6 (count), Example 1
+ * (emit), Theorem 1 (ascending result).
+ */
+int bitsort_u32(const uint32_t *keys, uint64_t n, uint32_t range_bits, uint32_t *out,
+                bitsort_stream_t stream);
+
+/* Bytes of caller workspace bitsort_u32_ws needs for (n, range_bits); 0 on
+ * invalid arguments. */
+size_t bitsort_workspace_bytes(uint64_t n, uint32_t range_bits);
+
+/*
+ * bitsort_u32 with a caller-provided device workspace of at least
+ * bitsort_workspace_bytes(n, range_bits) bytes, 256-byte aligned.  Its first
+ * sizeof(bitsort_status_t) bytes receive the status of this call; read them
+ * with bitsort_workspace_status().  Errors: as bitsort_u32, plus
+ * BITSORT_ERR_NO_MEMORY when ws_bytes is too small and BITSORT_ERR_INVALID_ARG
+ * when the workspace is misaligned.
+ */
+int bitsort_u32_ws(const uint32_t *keys, uint64_t n, uint32_t range_bits, uint32_t *out,
+                   void *workspace, size_t ws_bytes, bitsort_stream_t stream);
+
+/* Synchronise `stream`, then copy the status of the last call made on it
+ * (library workspace) into *status. */
+int bitsort_get_status(bitsort_stream_t stream, bitsort_status_t *status);
+
+/* Synchronise `stream`, then copy the status held in a caller workspace. */
+int bitsort_workspace_status(const void *workspace, bitsort_stream_t stream,
+                             bitsort_status_t *status);
+
+/*
+ * Segmented sort: num_segments independent arrays sorted by one persistent
+ * launch (each segment is the problem of bitsort_u32 with its own range).
+ *   keys          device uint32, offsets[num_segments] elements in all.
+ *   offsets       device uint64[num_segments + 1]; offsets[0] = 0 and
+ *                 non-decreasing; segment s is keys[offsets[s] .. offsets[s+1]).
+ *   num_segments  1 .. BITSORT_BATCH_MAX_SEGMENTS.
+ *   range_bits    device uint8[num_segments], each 0..BITSORT_BATCH_MAX_RANGE_BITS.
+ *   out           device uint32, same length as keys; must not overlap keys.
+ *   max_keys      host: the number of elements allocated for keys and for
+ *                 out.  A segment reaching past it is skipped and flagged
+ *                 BITSORT_STATUS_BAD_SEGMENT; also used for the overlap check.
+ * Segment s's sorted keys land in out[offsets[s] .. offsets[s] + d_s).  The
+ * segment sizes are read on the device, so the host never waits.  Per-segment
+ * statuses: bitsort_batch_status().  A segment with a decreasing offset or a
+ * range_bits above the limit is skipped and flagged BITSORT_STATUS_BAD_SEGMENT.
+ * With a duplicate key, the segment's output slots are unspecified (writes
+ * stay inside the segment) and BITSORT_STATUS_DUPLICATE is set.
+ */
+#define BITSORT_BATCH_MAX_RANGE_BITS 24
+#define BITSORT_BATCH_MAX_SEGMENTS (1u << 24)
+#define BITSORT_STATUS_BAD_SEGMENT 4u
+int bitsort_batch_u32(const uint32_t *keys, const uint64_t *offsets, uint32_t num_segments,
+                      const uint8_t *range_bits, uint32_t *out, uint64_t max_keys,
+                      bitsort_stream_t stream);
+
+/* Synchronise `stream`, then copy per-segment statuses of the last
+ * bitsort_batch_u32 on it into host status[0 .. num_segments). */
+int bitsort_batch_status(bitsort_stream_t stream, bitsort_status_t *status, uint32_t num_segments);
+
+/*
+ * Device-side input generator (the synthetic workloads): out[i] = pi(first + i)
+ * for i < count, where pi is the seeded keyed permutation of [0, 2^range_bits)
+ * (4-round Feistel network with cycle walking; round keys from SplitMix64).
+ * Gives distinct keys in pseudo-random order.  first + count <= 2^range_bits.
+ */
+int bitsort_generate_u32(uint32_t *out, uint64_t first, uint64_t count, uint32_t range_bits,
+                         uint64_t seed, bitsort_stream_t stream);
+
+/*
+ * Diagnostics that run the same device code as bitsort_u32 and stop at an
+ * intermediate step, for tests:
+ * - bitsort_debug_bitmap_u32: the mark step; writes the whole bit-vector,
+ *   max(1, 2^range_bits / 32) uint32 words, to device `bitmap` (word w bit b
+ *   set iff key 32w + b occurred).
+ * - bitsort_debug_prefix_u32: the scan step; writes, for every word w, the
+ *   number of set bits in words 0 .. w-1 to device uint64 `prefix` (one entry
+ *   per word).
+ * Both need range_bits <= 30 (the dump must fit in memory comfortably).
+ */
+int bitsort_debug_bitmap_u32(const uint32_t *keys, uint64_t n, uint32_t range_bits,
+                             uint32_t *bitmap, bitsort_stream_t stream);
+int bitsort_debug_prefix_u32(const uint32_t *keys, uint64_t n, uint32_t range_bits,
+                             uint64_t *prefix, bitsort_stream_t stream);
+
+/*
+ * Tuning knobs for the plain path (0 = library default).  slice_bits: bits
+ * of key range per LDS slice (10..20); tile_log2: keys per partition tile as
+ * a power of two (12..14).  Affects calls made afterwards in this process.
+ */
+int bitsort_set_tuning(uint32_t slice_bits, uint32_t tile_log2);
+
+/* The slice_bits and tile_log2 the plain path would use for (n, range_bits). */
+int bitsort_plan_info(uint64_t n, uint32_t range_bits, uint32_t *slice_bits, uint32_t *tile_log2,
+                      uint32_t *buckets);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BITSORT_H */

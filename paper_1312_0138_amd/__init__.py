@@ -1,0 +1,158 @@
+"""MI355X (gfx950) bitmap sort: distinct bounded uint32 keys sorted by marking
+one bit per key in LDS-resident bit-vector slices, then scanning the words
+and writing out the positions of the set bits (Yordzhev, arXiv:1312.0138).
+
+All work runs in the HIP kernels of ``libbitsort.so``; this package only
+hands torch device memory and streams to its C ABI (``_lib``) and raises on
+any error.  ``inputs`` holds the seeded synthetic workload generators.
+"""
+from __future__ import annotations
+
+from . import _lib
+from ._lib import (BitsortError, STATUS_BAD_SEGMENT, STATUS_DUPLICATE,
+                   STATUS_OUT_OF_RANGE, Status)
+
+__all__ = [
+    "sort", "status", "sort_batch", "batch_status", "generate", "debug_bitmap",
+    "debug_prefix", "workspace_bytes", "sort_ws", "workspace_status", "set_tuning",
+    "plan_info", "BitsortError", "Status", "STATUS_OUT_OF_RANGE", "STATUS_DUPLICATE",
+    "STATUS_BAD_SEGMENT",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _check_u32(t, name):
+    torch = _torch()
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype not in (torch.int32, torch.uint32):
+        raise TypeError(f"{name} must hold 32-bit keys (int32 or uint32), got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def sort(keys, range_bits: int, out=None, stream=None):
+    """Sort distinct keys in [0, 2^range_bits) ascending; returns ``out``."""
+    torch = _torch()
+    _check_u32(keys, "keys")
+    if out is None:
+        out = torch.empty_like(keys)
+    _check_u32(out, "out")
+    if out.numel() != keys.numel():
+        raise ValueError("out must have as many elements as keys")
+    _lib.check(_lib.bitsort_u32(keys.data_ptr(), keys.numel(), range_bits, out.data_ptr(), _stream(stream)),
+               "bitsort_u32")
+    return out
+
+
+def status(stream=None) -> Status:
+    """Synchronise the stream and return the status of its last ``sort``."""
+    rc, st = _lib.bitsort_get_status(_stream(stream))
+    _lib.check(rc, "bitsort_get_status")
+    return st
+
+
+def workspace_bytes(n: int, range_bits: int) -> int:
+    return _lib.bitsort_workspace_bytes(n, range_bits)
+
+
+def sort_ws(keys, range_bits: int, workspace, out=None, stream=None):
+    """``sort`` with a caller workspace (a uint8 device tensor)."""
+    torch = _torch()
+    _check_u32(keys, "keys")
+    if out is None:
+        out = torch.empty_like(keys)
+    _lib.check(_lib.bitsort_u32_ws(keys.data_ptr(), keys.numel(), range_bits, out.data_ptr(),
+                                   workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                   _stream(stream)), "bitsort_u32_ws")
+    return out
+
+
+def workspace_status(workspace, stream=None) -> Status:
+    rc, st = _lib.bitsort_workspace_status(workspace.data_ptr(), _stream(stream))
+    _lib.check(rc, "bitsort_workspace_status")
+    return st
+
+
+def sort_batch(keys, offsets, range_bits, out=None, stream=None):
+    """Sort every segment keys[offsets[s]:offsets[s+1]] on its own.
+
+    ``offsets`` is a device int64/uint64 tensor of num_segments + 1 entries,
+    ``range_bits`` a device uint8 tensor of num_segments entries."""
+    torch = _torch()
+    _check_u32(keys, "keys")
+    if out is None:
+        out = torch.empty_like(keys)
+    nseg = range_bits.numel()
+    if offsets.numel() != nseg + 1:
+        raise ValueError("offsets must have num_segments + 1 entries")
+    if offsets.dtype not in (torch.int64, torch.uint64) or range_bits.dtype != torch.uint8:
+        raise TypeError("offsets must be 64-bit and range_bits uint8")
+    if not (offsets.is_cuda and range_bits.is_cuda and offsets.is_contiguous() and range_bits.is_contiguous()):
+        raise ValueError("offsets and range_bits must be contiguous device tensors")
+    _lib.check(_lib.bitsort_batch_u32(keys.data_ptr(), offsets.data_ptr(), nseg, range_bits.data_ptr(),
+                                      out.data_ptr(), keys.numel(), _stream(stream)), "bitsort_batch_u32")
+    return out
+
+
+def batch_status(num_segments: int, stream=None):
+    """Synchronise; (flags, count) arrays of the last ``sort_batch``."""
+    import numpy as np
+    rc, arr = _lib.bitsort_batch_status(_stream(stream), num_segments)
+    _lib.check(rc, "bitsort_batch_status")
+    flags = np.array([arr[i].flags for i in range(num_segments)], dtype=np.uint32)
+    counts = np.array([arr[i].count for i in range(num_segments)], dtype=np.uint64)
+    return flags, counts
+
+
+def generate(count: int, range_bits: int, seed: int, first: int = 0, out=None, stream=None):
+    """Device twin of ``inputs.keyed_permutation``: pi(first .. first+count-1)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(count, dtype=torch.int32, device="cuda")
+    _lib.check(_lib.bitsort_generate_u32(out.data_ptr(), first, count, range_bits, seed, _stream(stream)),
+               "bitsort_generate_u32")
+    return out
+
+
+def debug_bitmap(keys, range_bits: int, stream=None):
+    """The mark step's bit-vector (max(1, 2^range_bits/32) int32 words)."""
+    torch = _torch()
+    _check_u32(keys, "keys")
+    words = max(1, (1 << range_bits) // 32)
+    bm = torch.zeros(words, dtype=torch.int32, device=keys.device)
+    _lib.check(_lib.bitsort_debug_bitmap_u32(keys.data_ptr(), keys.numel(), range_bits, bm.data_ptr(),
+                                             _stream(stream)), "bitsort_debug_bitmap_u32")
+    return bm
+
+
+def debug_prefix(keys, range_bits: int, stream=None):
+    """The scan step's exclusive per-word prefix of set bits (int64 words)."""
+    torch = _torch()
+    _check_u32(keys, "keys")
+    words = max(1, (1 << range_bits) // 32)
+    pre = torch.zeros(words, dtype=torch.int64, device=keys.device)
+    _lib.check(_lib.bitsort_debug_prefix_u32(keys.data_ptr(), keys.numel(), range_bits, pre.data_ptr(),
+                                             _stream(stream)), "bitsort_debug_prefix_u32")
+    return pre
+
+
+def set_tuning(slice_bits: int = 0, tile_log2: int = 0) -> None:
+    _lib.check(_lib.bitsort_set_tuning(slice_bits, tile_log2), "bitsort_set_tuning")
+
+
+def plan_info(n: int, range_bits: int):
+    rc, sb, tl, nb = _lib.bitsort_plan_info(n, range_bits)
+    _lib.check(rc, "bitsort_plan_info")
+    return {"slice_bits": sb, "tile_log2": tl, "buckets": nb}

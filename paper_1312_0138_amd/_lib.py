@@ -1,0 +1,154 @@
+"""ctypes binding of libbitsort.so: one Python function per C-ABI entry point,
+same names, argument marshalling only.  Raises if the library is not built --
+there is no fallback of any kind."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbitsort.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "bitsort.h")
+
+BITSORT_OK = 0
+BITSORT_ERR_INVALID_ARG = 1
+BITSORT_ERR_TOO_LARGE = 2
+BITSORT_ERR_NO_MEMORY = 3
+BITSORT_ERR_HIP = 4
+
+STATUS_OUT_OF_RANGE = 1
+STATUS_DUPLICATE = 2
+STATUS_BAD_SEGMENT = 4
+
+BATCH_MAX_RANGE_BITS = 24
+
+
+class BitsortError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: error {code} ({error_string(code) if _lib else '?'})")
+
+
+class Status(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("_pad", ctypes.c_uint32), ("count", ctypes.c_uint64)]
+
+
+_c = ctypes
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_SIGS = {
+    "bitsort_version": (_c.c_int, []),
+    "bitsort_error_string": (_c.c_char_p, [_c.c_int]),
+    "bitsort_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
+    "bitsort_workspace_bytes": (_c.c_size_t, [_u64, _u32]),
+    "bitsort_u32_ws": (_c.c_int, [_vp, _u64, _u32, _vp, _vp, _c.c_size_t, _vp]),
+    "bitsort_get_status": (_c.c_int, [_vp, _c.POINTER(Status)]),
+    "bitsort_workspace_status": (_c.c_int, [_vp, _vp, _c.POINTER(Status)]),
+    "bitsort_batch_u32": (_c.c_int, [_vp, _vp, _u32, _vp, _vp, _u64, _vp]),
+    "bitsort_batch_status": (_c.c_int, [_vp, _c.POINTER(Status), _u32]),
+    "bitsort_generate_u32": (_c.c_int, [_vp, _u64, _u64, _u32, _u64, _vp]),
+    "bitsort_debug_bitmap_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
+    "bitsort_debug_prefix_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
+    "bitsort_set_tuning": (_c.c_int, [_u32, _u32]),
+    "bitsort_plan_info": (_c.c_int, [_u64, _u32, _c.POINTER(_u32), _c.POINTER(_u32), _c.POINTER(_u32)]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library.  Raises FileNotFoundError when it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(
+                f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
+                "(hipcc, --offload-arch=gfx950)")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def header_symbols() -> list[str]:
+    """Every function the public header declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bitsort_[a-z0-9_]+)\s*\(", text)))
+
+
+def check(code: int, where: str) -> None:
+    if code != BITSORT_OK:
+        raise BitsortError(code, where)
+
+
+# ---- one wrapper per entry point (raw pointers / ints in, return code out) ----
+
+def bitsort_version() -> int:
+    return lib().bitsort_version()
+
+
+def error_string(code: int) -> str:
+    return lib().bitsort_error_string(code).decode()
+
+
+def bitsort_u32(keys: int, n: int, range_bits: int, out: int, stream: int) -> int:
+    return lib().bitsort_u32(keys, n, range_bits, out, stream)
+
+
+def bitsort_workspace_bytes(n: int, range_bits: int) -> int:
+    return lib().bitsort_workspace_bytes(n, range_bits)
+
+
+def bitsort_u32_ws(keys: int, n: int, range_bits: int, out: int, ws: int, ws_bytes: int, stream: int) -> int:
+    return lib().bitsort_u32_ws(keys, n, range_bits, out, ws, ws_bytes, stream)
+
+
+def bitsort_get_status(stream: int) -> tuple[int, Status]:
+    st = Status()
+    rc = lib().bitsort_get_status(stream, ctypes.byref(st))
+    return rc, st
+
+
+def bitsort_workspace_status(ws: int, stream: int) -> tuple[int, Status]:
+    st = Status()
+    rc = lib().bitsort_workspace_status(ws, stream, ctypes.byref(st))
+    return rc, st
+
+
+def bitsort_batch_u32(keys: int, offsets: int, num_segments: int, range_bits: int, out: int,
+                      max_keys: int, stream: int) -> int:
+    return lib().bitsort_batch_u32(keys, offsets, num_segments, range_bits, out, max_keys, stream)
+
+
+def bitsort_batch_status(stream: int, num_segments: int):
+    arr = (Status * max(num_segments, 1))()
+    rc = lib().bitsort_batch_status(stream, arr, num_segments)
+    return rc, arr
+
+
+def bitsort_generate_u32(out: int, first: int, count: int, range_bits: int, seed: int, stream: int) -> int:
+    return lib().bitsort_generate_u32(out, first, count, range_bits, seed & 0xFFFFFFFFFFFFFFFF, stream)
+
+
+def bitsort_debug_bitmap_u32(keys: int, n: int, range_bits: int, bitmap: int, stream: int) -> int:
+    return lib().bitsort_debug_bitmap_u32(keys, n, range_bits, bitmap, stream)
+
+
+def bitsort_debug_prefix_u32(keys: int, n: int, range_bits: int, prefix: int, stream: int) -> int:
+    return lib().bitsort_debug_prefix_u32(keys, n, range_bits, prefix, stream)
+
+
+def bitsort_set_tuning(slice_bits: int, tile_log2: int) -> int:
+    return lib().bitsort_set_tuning(slice_bits, tile_log2)
+
+
+def bitsort_plan_info(n: int, range_bits: int):
+    sb, tl, nb = _u32(), _u32(), _u32()
+    rc = lib().bitsort_plan_info(n, range_bits, ctypes.byref(sb), ctypes.byref(tl), ctypes.byref(nb))
+    return rc, sb.value, tl.value, nb.value

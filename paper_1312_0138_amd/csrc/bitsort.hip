@@ -1,0 +1,1001 @@
+// bitsort.hip -- gfx950 (MI355X) kernels and C ABI of the bitmap sort.
+//
+// The operation is the one of Yordzhev, arXiv:1312.0138: sort an integer
+// array ascending (Section IV, Theorem 1), done here the bit-vector way from
+// the primitives of Sections II-III: a key k is marked as bit (k & 31) of
+// word (k >> 5) with a shift and an OR (Table I, Examples 2 and 3); the words
+// are scanned in order, their ones counted (Example 6), and the position of
+// every set bit is written out, lowest bit first (Example 1; bit 0 is the
+// rightmost, Section II).
+//
+// MI355X design.  Global atomics on this part resolve at about 27 G ops/s no
+// matter the footprint, so marking n random keys straight into an HBM
+// bit-vector costs n atomics at that rate -- tens of times the streaming
+// time of the keys.  LDS atomics run at about 2-3 T ops/s.  So the bit-vector
+// never lives in HBM: it is cut into slices of 2^sb bits that fit in one
+// workgroup's LDS (up to 2^20 bits = 128 KiB of the 160 KiB), and the keys
+// are routed to their slice first:
+//
+//   k_partition  one workgroup per tile of T keys: counts keys per slice
+//                (LDS histogram), exclusive-scans the counts, groups the tile
+//                by slice in LDS and writes it back coalesced to a staging
+//                area at the tile's own offset, plus the tile's per-slice
+//                start offsets (a row of the tile table).
+//   k_slice      one workgroup per slice: clears its LDS slice, reads that
+//                slice's segment from every tile (64 keys per wave load, 8
+//                loads in flight per wave) and ORs the bits in with ds_or;
+//                then counts ones per word and prefix-sums them with ballot /
+//                mbcnt, and writes each word's set-bit positions (ctz, clear
+//                lowest bit) through an LDS staging buffer so that stores to
+//                `out` are contiguous.  The slice's output base -- the
+//                device-wide exclusive prefix over slices -- is the sum over
+//                tiles of the tile-local starts, read from the table with no
+//                extra pass.
+//   k_direct     a single workgroup for key ranges that fit one slice and
+//                small n: mark, scan and emit without the partition.
+//
+// HBM traffic of the two-kernel path: 4n (keys) + 4n + 4n (staging write and
+// read) + 4n (out) bytes plus the tile table; the bit-vector itself costs only
+// LDS bandwidth.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "bitsort.h"
+#include "bitsort_device.h"
+
+using namespace bitsort_dev;
+
+namespace {
+
+constexpr uint32_t kLdsBytes = 160 * 1024;    // LDS per workgroup on gfx950
+constexpr uint32_t kMaxSliceBits = 20;        // 2^20 bits = 128 KiB of LDS
+constexpr uint32_t kMinSliceBits = 10;
+constexpr uint32_t kMaxBucketsLog2 = 12;      // partition fan-out <= 4096
+constexpr uint32_t kSliceBlock = 1024;
+constexpr uint32_t kSliceUnroll = 8;
+constexpr uint32_t kDirectBlock = 1024;
+constexpr uint64_t kDirectMaxN = 8192;        // single-workgroup path below this
+constexpr uint32_t kHeaderBytes = 256;        // status + scratch header in LDS / workspace
+constexpr uint32_t kStageMax = 8192;
+constexpr uint32_t kBatchBlock = 1024;
+constexpr uint32_t kBatchSliceBits = 20;
+
+enum Mode : int { kEmit = 0, kDumpBitmap = 1, kDumpPrefix = 2 };
+
+__host__ __device__ constexpr uint32_t round_up4(uint32_t x) { return (x + 3u) & ~3u; }
+
+// ---------------------------------------------------------------------------
+// Scan and emit one LDS slice (Example 6 per word, then Example 1 per bit).
+//
+// slice[0 .. slice_words) holds the marked bits of keys key_base + 32*w + b.
+// Words are taken BLOCK at a time (one per thread): each thread counts the
+// ones of its word, the block forms the exclusive prefix p (ballot bit planes
+// + per-wave sums in LDS), and every set bit of the word is written to
+// stage[p + j - lo] for the window [lo, lo + stage_cap) of the chunk's output;
+// the window is then copied to out[out_base + done + lo ...] with contiguous
+// stores.  Returns the number of set bits (uniform).  Every thread calls it.
+template <int BLOCK>
+__device__ uint64_t scan_emit(const uint32_t* slice, uint32_t slice_words, uint32_t key_base,
+                              uint32_t* stage, uint32_t stage_cap, uint32_t* scratch,
+                              uint32_t* __restrict__ out, uint64_t out_base, int mode,
+                              uint32_t* dbg_bitmap, uint64_t* dbg_prefix, uint64_t dbg_word0) {
+  constexpr uint32_t kWaves = BLOCK / kWave;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & (kWave - 1);
+  const uint32_t wave = tid / kWave;
+  uint64_t done = 0;
+  for (uint32_t w0 = 0; w0 < slice_words; w0 += BLOCK) {
+    const uint32_t w = w0 + tid;
+    const uint32_t x = (w < slice_words) ? slice[w] : 0u;
+    const uint32_t c = static_cast<uint32_t>(__popc(x));
+    uint32_t wt;
+    const uint32_t wp = wave_prefix_small(c, &wt);
+    if (lane == 0) scratch[wave] = wt;
+    __syncthreads();
+    uint32_t wb = 0, ct = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kWaves; ++i) {
+      const uint32_t v = scratch[i];
+      wb += (i < wave) ? v : 0u;
+      ct += v;
+    }
+    ct = uniform(ct);
+    const uint32_t p = wb + wp;
+    if (mode == kDumpBitmap) {
+      if (w < slice_words) dbg_bitmap[dbg_word0 + w] = x;
+    } else if (mode == kDumpPrefix) {
+      if (w < slice_words) dbg_prefix[dbg_word0 + w] = out_base + done + p;
+    } else {
+      for (uint32_t lo = 0; lo < ct; lo += stage_cap) {
+        if (c != 0 && p < lo + stage_cap && p + c > lo) {
+          uint32_t y = x, pos = p;
+          while (pos < lo) {  // drop the bits that belong to earlier windows
+            y &= y - 1u;
+            ++pos;
+          }
+          const uint32_t kb = key_base + (w << 5);
+          while (y != 0u && pos < lo + stage_cap) {
+            stage[pos - lo] = kb + static_cast<uint32_t>(__builtin_ctz(y));
+            y &= y - 1u;
+            ++pos;
+          }
+        }
+        __syncthreads();
+        const uint32_t m = min(stage_cap, ct - lo);
+        uint32_t* dst = out + out_base + done + lo;
+        for (uint32_t i = tid; i < m; i += BLOCK) dst[i] = stage[i];
+        __syncthreads();
+      }
+    }
+    __syncthreads();  // scratch is rewritten by the next chunk
+    done += ct;
+  }
+  return done;
+}
+
+// One workgroup moves every slice's output left so that the slices' keys are
+// contiguous (only after a duplicate key made some slice write fewer keys
+// than its share).  binfo[2b] = where slice b wrote, binfo[2b+1] = how many.
+template <int BLOCK>
+__device__ void compact_slices(uint32_t* out, const uint64_t* binfo, uint32_t nb) {
+  uint64_t dst = 0;
+  for (uint32_t b = 0; b < nb; ++b) {
+    const uint64_t src = uniform(__hip_atomic_load(&binfo[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const uint64_t cnt = uniform(__hip_atomic_load(&binfo[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (src != dst) {
+      for (uint64_t i0 = 0; i0 < cnt; i0 += BLOCK) {
+        const uint64_t i = i0 + threadIdx.x;
+        uint32_t v = 0;
+        if (i < cnt) v = out[src + i];
+        __syncthreads();  // dst <= src: read this chunk before any thread overwrites it
+        if (i < cnt) out[dst + i] = v;
+        __syncthreads();
+      }
+    }
+    dst += cnt;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Partition: route each key of a tile to its slice (mark, first half).
+//
+// LDS: [scratch 32 words][hist nb words, padded to 4][tile keys T words].
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t* __restrict__ keys, uint64_t n,
+                                                     uint64_t range, uint32_t sb, uint32_t nb,
+                                                     uint32_t* __restrict__ staging,
+                                                     uint32_t* __restrict__ table, Status* status,
+                                                     int vec_ok) {
+  static_assert(ITEMS % 4 == 0, "ITEMS must be a multiple of 4");
+  constexpr uint32_t T = BLOCK * ITEMS;
+  extern __shared__ __align__(16) uint32_t lds[];
+  uint32_t* scratch = lds;
+  uint32_t* hist = lds + 32;
+  uint32_t* tk = lds + 32 + round_up4(nb);
+  const uint32_t tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) {
+    status->flags = 0;
+    status->done = 0;
+    status->count = 0;
+  }
+  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * T;
+  const uint32_t cnt = static_cast<uint32_t>(min(static_cast<uint64_t>(T), n - base));
+  for (uint32_t i = tid; i < nb; i += BLOCK) hist[i] = 0u;
+  __syncthreads();
+
+  uint32_t k[ITEMS], r[ITEMS];
+  if (vec_ok && cnt == T) {
+    const uint4* src = reinterpret_cast<const uint4*>(keys + base);
+#pragma unroll
+    for (int j = 0; j < ITEMS / 4; ++j) {
+      const uint4 q = src[tid + j * BLOCK];
+      k[4 * j] = q.x;
+      k[4 * j + 1] = q.y;
+      k[4 * j + 2] = q.z;
+      k[4 * j + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < ITEMS / 4; ++j)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const uint32_t idx = (tid + j * BLOCK) * 4u + c;
+        k[4 * j + c] = idx < cnt ? keys[base + idx] : 0u;
+      }
+  }
+  // Rank of each key inside its slice's group (order inside a group is
+  // irrelevant: the slice ORs them).  Keys >= range are dropped here.
+#pragma unroll
+  for (int j = 0; j < ITEMS / 4; ++j)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = 4 * j + c;
+      const uint32_t idx = (tid + j * BLOCK) * 4u + c;
+      const bool valid = idx < cnt && static_cast<uint64_t>(k[i]) < range;
+      r[i] = valid ? atomicAdd(&hist[k[i] >> sb], 1u) : 0xFFFFFFFFu;
+    }
+  __syncthreads();
+
+  // Exclusive scan of the nb counts -> group starts; also the table row.
+  const uint32_t per = (nb + BLOCK - 1) / BLOCK;
+  const uint32_t lo = tid * per;
+  uint32_t s = 0;
+  for (uint32_t e = 0; e < per; ++e)
+    if (lo + e < nb) s += hist[lo + e];
+  uint32_t tot;
+  const uint32_t pre = block_excl_scan<BLOCK>(s, scratch, &tot);
+  uint32_t* row = table + static_cast<uint64_t>(blockIdx.x) * (nb + 1u);
+  uint32_t run = pre;
+  for (uint32_t e = 0; e < per; ++e)
+    if (lo + e < nb) {
+      const uint32_t h = hist[lo + e];
+      hist[lo + e] = run;
+      row[lo + e] = run;
+      run += h;
+    }
+  if (tid == 0) row[nb] = tot;
+  __syncthreads();
+
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i)
+    if (r[i] != 0xFFFFFFFFu) tk[hist[k[i] >> sb] + r[i]] = k[i];
+  __syncthreads();
+
+  uint32_t* dst = staging + base;
+  const uint32_t n4 = tot >> 2;
+  const uint4* tk4 = reinterpret_cast<const uint4*>(tk);
+  uint4* dst4 = reinterpret_cast<uint4*>(dst);
+  for (uint32_t i = tid; i < n4; i += BLOCK) dst4[i] = tk4[i];
+  for (uint32_t i = (n4 << 2) + tid; i < tot; i += BLOCK) dst[i] = tk[i];
+}
+
+// ---------------------------------------------------------------------------
+// Slice: mark (second half), scan and emit one slice b = blockIdx.x.
+//
+// LDS: [scratch64 16 u64][scratch 32 words][slice 2^sb bits][stage].
+template <int BLOCK, int UNROLL>
+__global__ __launch_bounds__(BLOCK) void k_slice(const uint32_t* __restrict__ staging,
+                                                 const uint32_t* __restrict__ table, uint32_t nt,
+                                                 uint32_t tile_keys, uint64_t n, uint32_t sb,
+                                                 uint32_t nb, uint32_t stage_cap,
+                                                 uint32_t* __restrict__ out, Status* status,
+                                                 uint64_t* __restrict__ binfo, int mode,
+                                                 uint32_t* dbg_bitmap, uint64_t* dbg_prefix) {
+  constexpr uint32_t kWaves = BLOCK / kWave;
+  extern __shared__ __align__(16) uint32_t lds[];
+  uint64_t* scratch64 = reinterpret_cast<uint64_t*>(lds);
+  uint32_t* scratch = lds + 32;
+  uint32_t* slice = lds + 64;
+  const uint32_t slice_words = (sb >= 5) ? (1u << (sb - 5)) : 1u;
+  uint32_t* stage = slice + round_up4(slice_words);
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & (kWave - 1);
+  const uint32_t wave = tid / kWave;
+  const uint32_t b = blockIdx.x;
+
+  for (uint32_t i = tid; i < slice_words; i += BLOCK) slice[i] = 0u;
+  __syncthreads();
+
+  // Mark: the wave takes 64 tiles at a time (lane l <-> tile t0 + l), turns
+  // their segments for slice b into 64-key units, and each unit is one
+  // coalesced load of 64 keys followed by 64 ds_or (Table I's OR).
+  const uint32_t smask = (1u << sb) - 1u;
+  uint64_t base_acc = 0, cnt_acc = 0;
+  for (uint32_t t0 = wave * kWave; t0 < nt; t0 += kWaves * kWave) {
+    const uint32_t t = t0 + lane;
+    uint32_t s = 0, e = 0;
+    if (t < nt) {
+      const uint32_t* row = table + static_cast<uint64_t>(t) * (nb + 1u);
+      s = row[b];
+      e = row[b + 1u];
+    }
+    base_acc += s;
+    cnt_acc += e - s;
+    const uint32_t units = (e - s + kWave - 1u) / kWave;
+    const uint32_t inc = wave_incl_scan(units);
+    const uint32_t upre = inc - units;
+    const uint32_t utot = uniform(static_cast<uint32_t>(__shfl(inc, kWave - 1, kWave)));
+    for (uint32_t u0 = 0; u0 < utot; u0 += UNROLL) {
+      uint32_t kk[UNROLL];
+      bool vv[UNROLL];
+#pragma unroll
+      for (int q = 0; q < UNROLL; ++q) {
+        const uint32_t u = u0 + q;
+        vv[q] = false;
+        kk[q] = 0u;
+        if (u < utot) {
+          // Owner of unit u: the last lane whose unit prefix is <= u.
+          const uint64_t m = __ballot(upre <= u);
+          const uint32_t j = static_cast<uint32_t>(__popcll(m)) - 1u;
+          const uint32_t sj = __shfl(s, j, kWave);
+          const uint32_t ej = __shfl(e, j, kWave);
+          const uint32_t pj = __shfl(upre, j, kWave);
+          const uint32_t idx = sj + (u - pj) * kWave + lane;
+          if (idx < ej) {
+            kk[q] = staging[static_cast<uint64_t>(t0 + j) * tile_keys + idx];
+            vv[q] = true;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < UNROLL; ++q)
+        if (vv[q]) {
+          const uint32_t l = kk[q] & smask;
+          atomicOr(&slice[l >> 5], 1u << (l & 31u));
+        }
+    }
+  }
+  const uint64_t base_b = block_sum_u64<BLOCK>(base_acc, scratch64);
+  const uint64_t cnt_b = block_sum_u64<BLOCK>(cnt_acc, scratch64);
+
+  const uint32_t key_base = b << sb;
+  const uint64_t pop = scan_emit<BLOCK>(slice, slice_words, key_base, stage, stage_cap, scratch, out,
+                                        base_b, mode, dbg_bitmap, dbg_prefix,
+                                        static_cast<uint64_t>(b) * slice_words);
+  if (mode != kEmit) return;
+
+  if (tid == 0) {
+    binfo[2 * b] = base_b;
+    binfo[2 * b + 1] = pop;
+    uint32_t f = 0;
+    if (pop != cnt_b) f |= BITSORT_STATUS_DUPLICATE;
+    if (b == nb - 1u && base_b + cnt_b != n) f |= BITSORT_STATUS_OUT_OF_RANGE;
+    if (f) atomicOr(&status->flags, f);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&status->count),
+              static_cast<unsigned long long>(pop));
+  }
+  // The last slice to finish compacts the output if a duplicate left gaps.
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) scratch[0] = (atomicAdd(&status->done, 1u) == nb - 1u) ? 1u : 0u;
+  __syncthreads();
+  if (uniform(scratch[0])) {
+    __threadfence();
+    if (uniform(atomic_load_flags(&status->flags)) & BITSORT_STATUS_DUPLICATE) compact_slices<BLOCK>(out, binfo, nb);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Direct: one workgroup, the key range fits one LDS slice (range <= 2^sb).
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_direct(const uint32_t* __restrict__ keys, uint64_t n,
+                                                  uint64_t range, uint32_t sb, uint32_t stage_cap,
+                                                  uint32_t* out, Status* status, int mode,
+                                                  uint32_t* dbg_bitmap, uint64_t* dbg_prefix) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  uint64_t* scratch64 = reinterpret_cast<uint64_t*>(lds);
+  uint32_t* scratch = lds + 32;
+  uint32_t* slice = lds + 64;
+  const uint32_t slice_words = (sb >= 5) ? (1u << (sb - 5)) : 1u;
+  uint32_t* stage = slice + round_up4(slice_words);
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < slice_words; i += BLOCK) slice[i] = 0u;
+  __syncthreads();
+  uint64_t valid = 0;
+  for (uint64_t i = tid; i < n; i += BLOCK) {
+    const uint32_t key = keys[i];
+    if (static_cast<uint64_t>(key) < range) {
+      ++valid;
+      atomicOr(&slice[key >> 5], 1u << (key & 31u));
+    }
+  }
+  valid = block_sum_u64<BLOCK>(valid, scratch64);  // also orders marks before the scan
+  const uint64_t pop = scan_emit<BLOCK>(slice, slice_words, 0u, stage, stage_cap, scratch, out, 0,
+                                        mode, dbg_bitmap, dbg_prefix, 0);
+  if (mode == kEmit && tid == 0) {
+    uint32_t f = 0;
+    if (valid != n) f |= BITSORT_STATUS_OUT_OF_RANGE;
+    if (pop != valid) f |= BITSORT_STATUS_DUPLICATE;
+    status->flags = f;
+    status->done = 0;
+    status->count = pop;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Seeded keyed permutation of [0, 2^bits) (synthetic inputs): 4-round
+// balanced Feistel network over d = bits rounded up to even, with cycle
+// walking back into [0, 2^bits) when bits is odd.
+__device__ __forceinline__ uint32_t feistel_round(uint32_t r, uint32_t k) {
+  uint32_t x = r ^ k;
+  x *= 0x9E3779B1u;
+  x ^= x >> 15;
+  x *= 0x85EBCA77u;
+  x ^= x >> 13;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t feistel_even(uint32_t x, uint32_t d, uint32_t k0, uint32_t k1,
+                                                 uint32_t k2, uint32_t k3) {
+  const uint32_t h = d >> 1;
+  const uint32_t m = (1u << h) - 1u;
+  uint32_t left = x >> h, right = x & m;
+  const uint32_t rk[4] = {k0, k1, k2, k3};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t t = right;
+    right = left ^ (feistel_round(right, rk[i]) & m);
+    left = t;
+  }
+  return (left << h) | right;
+}
+
+__global__ void k_generate(uint32_t* __restrict__ out, uint64_t first, uint64_t count, uint32_t bits,
+                           uint32_t k0, uint32_t k1, uint32_t k2, uint32_t k3) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  const uint32_t d = bits + (bits & 1u);
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) {
+    if (bits == 0) {
+      out[i] = 0u;
+      continue;
+    }
+    uint32_t y = feistel_even(static_cast<uint32_t>(first + i), d, k0, k1, k2, k3);
+    if (d != bits) {
+      // Cycle walking ends: the cycle through x returns to x < 2^bits.
+      const uint32_t lim = 1u << bits;
+      while (y >= lim) y = feistel_even(y, d, k0, k1, k2, k3);
+    }
+    out[i] = y;
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Batch: many independent segments, one persistent launch.
+//
+// Work items are (segment, slice) pairs; a segment with range 2^rb has
+// 2^(rb - sbb) slices of 2^sbb bits (one if rb <= sbb).  k_batch_plan lays
+// the items out largest range first (so the long items start early) and
+// k_batch_run's workgroups pull items from an atomic counter until none is
+// left.  An item reads its whole segment, keeps the keys of its slice (LDS
+// mark), counts the keys below the slice -- with distinct keys that count is
+// the slice's output offset inside the segment -- then scans and emits like
+// k_slice.  No workgroup waits on another.
+
+struct SegStatus {
+  uint32_t flags;
+  uint32_t pad;
+  uint64_t count;
+};
+
+constexpr uint32_t kMaxBatchRangeBits = BITSORT_BATCH_MAX_RANGE_BITS;
+
+__global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict__ offsets,
+                                                     const uint8_t* __restrict__ rbits, uint32_t nseg,
+                                                     uint64_t max_keys, uint32_t sbb,
+                                                     uint2* __restrict__ items,
+                                                     uint32_t* __restrict__ counter,
+                                                     SegStatus* __restrict__ seg_status) {
+  __shared__ uint32_t cls_items[kMaxBatchRangeBits + 1];
+  __shared__ uint32_t cls_cursor[kMaxBatchRangeBits + 1];
+  const uint32_t tid = threadIdx.x;
+  if (tid <= kMaxBatchRangeBits) cls_items[tid] = 0u;
+  __syncthreads();
+  for (uint32_t s = tid; s < nseg; s += blockDim.x) {
+    seg_status[s].flags = 0u;
+    seg_status[s].pad = 0u;
+    seg_status[s].count = 0ull;
+    const uint32_t rb = rbits[s];
+    if (rb > kMaxBatchRangeBits || offsets[s + 1] < offsets[s] || offsets[s + 1] > max_keys) continue;
+    const uint32_t ns = rb > sbb ? (1u << (rb - sbb)) : 1u;
+    atomicAdd(&cls_items[rb], ns);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t run = 0;
+    for (int c = static_cast<int>(kMaxBatchRangeBits); c >= 0; --c) {  // widest ranges first
+      cls_cursor[c] = run;
+      run += cls_items[c];
+    }
+    counter[0] = 0u;
+    counter[1] = run;
+  }
+  __syncthreads();
+  for (uint32_t s = tid; s < nseg; s += blockDim.x) {
+    const uint32_t rb = rbits[s];
+    if (rb > kMaxBatchRangeBits || offsets[s + 1] < offsets[s] || offsets[s + 1] > max_keys) {
+      seg_status[s].flags = BITSORT_STATUS_BAD_SEGMENT;
+      continue;
+    }
+    const uint32_t ns = rb > sbb ? (1u << (rb - sbb)) : 1u;
+    const uint32_t pos = atomicAdd(&cls_cursor[rb], ns);
+    for (uint32_t j = 0; j < ns; ++j) items[pos + j] = make_uint2(s, j);
+  }
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_batch_run(const uint32_t* __restrict__ keys,
+                                                     const uint64_t* __restrict__ offsets,
+                                                     const uint8_t* __restrict__ rbits, uint32_t sbb,
+                                                     uint32_t stage_cap, const uint2* __restrict__ items,
+                                                     uint32_t* counter, uint32_t* __restrict__ out,
+                                                     SegStatus* seg_status) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  uint64_t* scratch64 = reinterpret_cast<uint64_t*>(lds);
+  uint32_t* scratch = lds + 32;
+  uint32_t* slice = lds + 64;
+  const uint32_t max_words = sbb >= 5 ? (1u << (sbb - 5)) : 1u;
+  uint32_t* stage = slice + round_up4(max_words);
+  const uint32_t tid = threadIdx.x;
+  const uint32_t total = uniform(__hip_atomic_load(&counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  for (;;) {
+    if (tid == 0) scratch[0] = atomicAdd(&counter[0], 1u);
+    __syncthreads();
+    const uint32_t it = uniform(scratch[0]);
+    __syncthreads();
+    if (it >= total) break;  // every workgroup leaves once the items run out
+    const uint2 item = items[it];
+    const uint32_t s = uniform(item.x), j = uniform(item.y);
+    const uint64_t lo = uniform(offsets[s]), hi = uniform(offsets[s + 1]);
+    const uint32_t rb = uniform(static_cast<uint32_t>(rbits[s]));
+    const uint32_t sb = min(rb, sbb);
+    const uint32_t words = sb >= 5 ? (1u << (sb - 5)) : 1u;
+    const uint64_t range = 1ull << rb;
+    for (uint32_t i = tid; i < words; i += BLOCK) slice[i] = 0u;
+    __syncthreads();
+    uint64_t below = 0, mine = 0, valid = 0;
+    const uint32_t smask = (1u << sb) - 1u;
+    uint64_t i = lo + tid;
+    for (; i + 3ull * BLOCK < hi; i += 4ull * BLOCK) {
+      uint32_t kq[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) kq[q] = keys[i + static_cast<uint64_t>(q) * BLOCK];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t key = kq[q];
+        if (static_cast<uint64_t>(key) < range) {
+          ++valid;
+          const uint32_t sl = key >> sb;
+          below += sl < j ? 1u : 0u;
+          if (sl == j) {
+            ++mine;
+            const uint32_t l = key & smask;
+            atomicOr(&slice[l >> 5], 1u << (l & 31u));
+          }
+        }
+      }
+    }
+    for (; i < hi; i += BLOCK) {
+      const uint32_t key = keys[i];
+      if (static_cast<uint64_t>(key) < range) {
+        ++valid;
+        const uint32_t sl = key >> sb;
+        below += sl < j ? 1u : 0u;
+        if (sl == j) {
+          ++mine;
+          const uint32_t l = key & smask;
+          atomicOr(&slice[l >> 5], 1u << (l & 31u));
+        }
+      }
+    }
+    below = block_sum_u64<BLOCK>(below, scratch64);
+    mine = block_sum_u64<BLOCK>(mine, scratch64);
+    valid = block_sum_u64<BLOCK>(valid, scratch64);
+    const uint64_t pop = scan_emit<BLOCK>(slice, words, j << sb, stage, stage_cap, scratch, out, lo + below,
+                                          kEmit, nullptr, nullptr, 0);
+    if (tid == 0) {
+      uint32_t f = 0;
+      if (pop != mine) f |= BITSORT_STATUS_DUPLICATE;
+      if (j == 0 && valid != hi - lo) f |= BITSORT_STATUS_OUT_OF_RANGE;
+      if (f) atomicOr(&seg_status[s].flags, f);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&seg_status[s].count),
+                static_cast<unsigned long long>(pop));
+    }
+    __syncthreads();  // close the single-lane region before the next item's ticket
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+struct Plan {
+  uint32_t rb = 0, sb = 0, nb = 1, tile_log2 = 0, tile_keys = 0, nt = 0;
+  bool direct = true;
+  size_t off_binfo = 0, off_table = 0, off_staging = 0, bytes = 0;
+  uint32_t stage_cap = 0;
+  size_t slice_lds = 0;
+};
+
+std::atomic<uint32_t> g_tune_sb{0};
+std::atomic<uint32_t> g_tune_tile{0};
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+uint32_t stage_cap_for(uint32_t sb) {
+  const uint32_t slice_words = sb >= 5 ? (1u << (sb - 5)) : 1u;
+  const uint32_t used = kHeaderBytes + round_up4(slice_words) * 4u;
+  uint32_t cap = (kLdsBytes - used) / 4u;
+  cap = std::min(cap, kStageMax);
+  return cap & ~3u;
+}
+
+size_t slice_lds_bytes(uint32_t sb, uint32_t stage_cap) {
+  const uint32_t slice_words = sb >= 5 ? (1u << (sb - 5)) : 1u;
+  return kHeaderBytes + round_up4(slice_words) * 4u + static_cast<size_t>(stage_cap) * 4u;
+}
+
+void make_plan(uint64_t n, uint32_t rb, Plan* p) {
+  *p = Plan();
+  p->rb = rb;
+  if (rb <= kMinSliceBits || (rb <= kMaxSliceBits && n <= kDirectMaxN)) {
+    p->direct = true;
+    p->sb = rb;
+    p->nb = 1;
+    p->bytes = kHeaderBytes;
+  } else {
+    p->direct = false;
+    uint32_t sb = g_tune_sb.load();
+    if (sb == 0) sb = rb > 8 ? rb - 8 : rb;  // aim at 256 slices
+    const uint32_t lo = std::max<uint32_t>(std::min(rb, kMinSliceBits), rb > kMaxBucketsLog2 ? rb - kMaxBucketsLog2 : 0);
+    sb = std::max(sb, lo);
+    sb = std::min({sb, kMaxSliceBits, rb});
+    p->sb = sb;
+    p->nb = 1u << (rb - sb);
+    uint32_t tl = g_tune_tile.load();
+    if (tl == 0) tl = n >= (1ull << 22) ? 14 : 12;
+    tl = std::min<uint32_t>(std::max<uint32_t>(tl, 12), 14);
+    p->tile_log2 = tl;
+    p->tile_keys = 1u << tl;
+    p->nt = static_cast<uint32_t>((n + p->tile_keys - 1) >> tl);
+    p->off_binfo = kHeaderBytes;
+    p->off_table = align256(p->off_binfo + 16ull * p->nb);
+    p->off_staging = align256(p->off_table + 4ull * p->nt * (p->nb + 1));
+    p->bytes = align256(p->off_staging + 4ull * p->nt * p->tile_keys);
+  }
+  p->stage_cap = stage_cap_for(p->sb);
+  p->slice_lds = slice_lds_bytes(p->sb, p->stage_cap);
+}
+
+int check_args(const uint32_t* keys, uint64_t n, uint32_t rb, const uint32_t* out) {
+  if (rb > 32) return BITSORT_ERR_INVALID_ARG;
+  if (n > 0 && (keys == nullptr || out == nullptr)) return BITSORT_ERR_INVALID_ARG;
+  if (n >= (1ull << 32)) return BITSORT_ERR_TOO_LARGE;
+  if (n > (1ull << rb)) return BITSORT_ERR_TOO_LARGE;
+  if (n > 0 && keys != out) {
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(keys), a1 = a0 + 4 * n;
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(out), b1 = b0 + 4 * n;
+    if (a0 < b1 && b0 < a1) return BITSORT_ERR_INVALID_ARG;
+  }
+  return BITSORT_OK;
+}
+
+std::once_flag g_attr_once;
+hipError_t g_attr_err = hipSuccess;
+
+template <typename K>
+void set_lds_attr(K kernel, uint32_t bytes) {
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           static_cast<int>(bytes));
+  if (e != hipSuccess && g_attr_err == hipSuccess) g_attr_err = e;
+}
+
+int init_kernels() {
+  std::call_once(g_attr_once, [] {
+    set_lds_attr(k_partition<256, 16>, kLdsBytes);
+    set_lds_attr(k_partition<512, 16>, kLdsBytes);
+    set_lds_attr(k_partition<1024, 16>, kLdsBytes);
+    set_lds_attr(k_slice<kSliceBlock, kSliceUnroll>, kLdsBytes);
+    set_lds_attr(k_direct<kDirectBlock>, kLdsBytes);
+    set_lds_attr(k_batch_run<kBatchBlock>, kLdsBytes);
+  });
+  return g_attr_err == hipSuccess ? BITSORT_OK : BITSORT_ERR_HIP;
+}
+
+int launch_status() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BITSORT_OK : BITSORT_ERR_HIP;
+}
+
+// Enqueue the plain path.  mode != kEmit writes the debug dumps instead.
+int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, void* ws,
+              hipStream_t stream, int mode, uint32_t* dbg_bitmap, uint64_t* dbg_prefix) {
+  int rc = init_kernels();
+  if (rc != BITSORT_OK) return rc;
+  char* base = static_cast<char*>(ws);
+  Status* status = reinterpret_cast<Status*>(base);
+  const uint64_t range = 1ull << p.rb;
+  if (p.direct) {
+    hipLaunchKernelGGL(k_direct<kDirectBlock>, dim3(1), dim3(kDirectBlock), p.slice_lds, stream, keys, n,
+                       range, p.sb, p.stage_cap, out, status, mode, dbg_bitmap, dbg_prefix);
+    return launch_status();
+  }
+  uint32_t* table = reinterpret_cast<uint32_t*>(base + p.off_table);
+  uint32_t* staging = reinterpret_cast<uint32_t*>(base + p.off_staging);
+  uint64_t* binfo = reinterpret_cast<uint64_t*>(base + p.off_binfo);
+  const int vec_ok = (reinterpret_cast<uintptr_t>(keys) % 16u) == 0 ? 1 : 0;
+  const size_t part_lds = 4ull * (32 + round_up4(p.nb) + p.tile_keys);
+  switch (p.tile_log2) {
+    case 12:
+      hipLaunchKernelGGL((k_partition<256, 16>), dim3(p.nt), dim3(256), part_lds, stream, keys, n, range,
+                         p.sb, p.nb, staging, table, status, vec_ok);
+      break;
+    case 13:
+      hipLaunchKernelGGL((k_partition<512, 16>), dim3(p.nt), dim3(512), part_lds, stream, keys, n, range,
+                         p.sb, p.nb, staging, table, status, vec_ok);
+      break;
+    default:
+      hipLaunchKernelGGL((k_partition<1024, 16>), dim3(p.nt), dim3(1024), part_lds, stream, keys, n, range,
+                         p.sb, p.nb, staging, table, status, vec_ok);
+      break;
+  }
+  rc = launch_status();
+  if (rc != BITSORT_OK) return rc;
+  hipLaunchKernelGGL((k_slice<kSliceBlock, kSliceUnroll>), dim3(p.nb), dim3(kSliceBlock), p.slice_lds, stream,
+                     staging, table, p.nt, p.tile_keys, n, p.sb, p.nb, p.stage_cap, out, status, binfo, mode,
+                     dbg_bitmap, dbg_prefix);
+  return launch_status();
+}
+
+// Library-owned workspaces, one per (device, stream).
+struct StreamCtx {
+  void* ws = nullptr;
+  size_t bytes = 0;
+  bool last_empty = true;  // last call had n == 0 (status is all zero)
+  bool used = false;
+  void* batch_ws = nullptr;
+  size_t batch_bytes = 0;
+  uint32_t batch_segments = 0;
+};
+std::mutex g_mu;
+std::map<std::pair<int, void*>, StreamCtx> g_ctx;
+
+StreamCtx& ctx_for(bitsort_stream_t stream) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  return g_ctx[{dev, stream}];
+}
+
+int grow(void** ptr, size_t* have, size_t need, hipStream_t stream) {
+  if (*have >= need && *ptr != nullptr) return BITSORT_OK;
+  if (*ptr != nullptr) {
+    if (hipStreamSynchronize(stream) != hipSuccess) return BITSORT_ERR_HIP;
+    if (hipFree(*ptr) != hipSuccess) return BITSORT_ERR_HIP;
+    *ptr = nullptr;
+    *have = 0;
+  }
+  const size_t sz = std::max<size_t>(align256(need), 1 << 20);
+  if (hipMalloc(ptr, sz) != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return BITSORT_ERR_NO_MEMORY;
+  }
+  *have = sz;
+  return BITSORT_OK;
+}
+
+int copy_status(const void* dev_status, hipStream_t stream, bitsort_status_t* st) {
+  if (hipStreamSynchronize(stream) != hipSuccess) return BITSORT_ERR_HIP;
+  Status s{};
+  if (hipMemcpy(&s, dev_status, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess) return BITSORT_ERR_HIP;
+  st->flags = s.flags;
+  st->_pad = 0;
+  st->count = s.count;
+  return BITSORT_OK;
+}
+
+void splitmix_keys(uint64_t seed, uint32_t k[4]) {
+  uint64_t st = seed;
+  for (int i = 0; i < 4; ++i) {
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    k[i] = static_cast<uint32_t>(z);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI.
+
+extern "C" {
+
+int bitsort_version(void) { return 10000; }
+
+const char* bitsort_error_string(int code) {
+  switch (code) {
+    case BITSORT_OK: return "ok";
+    case BITSORT_ERR_INVALID_ARG: return "invalid argument";
+    case BITSORT_ERR_TOO_LARGE: return "problem too large (n > 2^range_bits, n >= 2^32, or a stated limit)";
+    case BITSORT_ERR_NO_MEMORY: return "out of device memory or workspace too small";
+    case BITSORT_ERR_HIP: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+size_t bitsort_workspace_bytes(uint64_t n, uint32_t range_bits) {
+  if (range_bits > 32 || n >= (1ull << 32) || n > (1ull << range_bits)) return 0;
+  Plan p;
+  make_plan(n, range_bits, &p);
+  return p.bytes;
+}
+
+int bitsort_u32_ws(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32_t* out, void* workspace,
+                   size_t ws_bytes, bitsort_stream_t stream) {
+  int rc = check_args(keys, n, range_bits, out);
+  if (rc != BITSORT_OK) return rc;
+  if (workspace == nullptr || (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return BITSORT_ERR_INVALID_ARG;
+  Plan p;
+  make_plan(n, range_bits, &p);
+  if (ws_bytes < p.bytes) return BITSORT_ERR_NO_MEMORY;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n == 0) {
+    return hipMemsetAsync(workspace, 0, sizeof(Status), s) == hipSuccess ? BITSORT_OK : BITSORT_ERR_HIP;
+  }
+  return run_plain(p, keys, n, out, workspace, s, kEmit, nullptr, nullptr);
+}
+
+int bitsort_u32(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32_t* out, bitsort_stream_t stream) {
+  int rc = check_args(keys, n, range_bits, out);
+  if (rc != BITSORT_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  StreamCtx& c = ctx_for(stream);
+  c.used = true;
+  if (n == 0) {
+    c.last_empty = true;
+    return BITSORT_OK;
+  }
+  Plan p;
+  make_plan(n, range_bits, &p);
+  rc = grow(&c.ws, &c.bytes, p.bytes, s);
+  if (rc != BITSORT_OK) return rc;
+  c.last_empty = false;
+  return run_plain(p, keys, n, out, c.ws, s, kEmit, nullptr, nullptr);
+}
+
+int bitsort_get_status(bitsort_stream_t stream, bitsort_status_t* status) {
+  if (status == nullptr) return BITSORT_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    StreamCtx& c = ctx_for(stream);
+    if (!c.used) return BITSORT_ERR_INVALID_ARG;
+    if (c.last_empty) {
+      if (hipStreamSynchronize(s) != hipSuccess) return BITSORT_ERR_HIP;
+      *status = bitsort_status_t{0, 0, 0};
+      return BITSORT_OK;
+    }
+    ws = c.ws;
+  }
+  return copy_status(ws, s, status);
+}
+
+int bitsort_workspace_status(const void* workspace, bitsort_stream_t stream, bitsort_status_t* status) {
+  if (workspace == nullptr || status == nullptr) return BITSORT_ERR_INVALID_ARG;
+  return copy_status(workspace, static_cast<hipStream_t>(stream), status);
+}
+
+int bitsort_generate_u32(uint32_t* out, uint64_t first, uint64_t count, uint32_t range_bits, uint64_t seed,
+                         bitsort_stream_t stream) {
+  if (range_bits > 32 || (count > 0 && out == nullptr)) return BITSORT_ERR_INVALID_ARG;
+  if (first + count > (1ull << range_bits) || first + count < first) return BITSORT_ERR_TOO_LARGE;
+  if (count == 0) return BITSORT_OK;
+  uint32_t k[4];
+  splitmix_keys(seed, k);
+  const uint64_t blocks = std::min<uint64_t>((count + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_generate, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), out, first, count, range_bits, k[0], k[1], k[2], k[3]);
+  return launch_status();
+}
+
+static int debug_run(const uint32_t* keys, uint64_t n, uint32_t range_bits, int mode, uint32_t* bm,
+                     uint64_t* pre, bitsort_stream_t stream) {
+  if (range_bits > 30 || (n > 0 && keys == nullptr)) return BITSORT_ERR_INVALID_ARG;
+  if (mode == kDumpBitmap && bm == nullptr) return BITSORT_ERR_INVALID_ARG;
+  if (mode == kDumpPrefix && pre == nullptr) return BITSORT_ERR_INVALID_ARG;
+  if (n > (1ull << range_bits)) return BITSORT_ERR_TOO_LARGE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Plan p;
+  make_plan(n, range_bits, &p);
+  void* ws = nullptr;
+  if (hipMalloc(&ws, p.bytes) != hipSuccess) return BITSORT_ERR_NO_MEMORY;
+  int rc = run_plain(p, keys, n, nullptr, ws, s, mode, bm, pre);
+  if (hipStreamSynchronize(s) != hipSuccess && rc == BITSORT_OK) rc = BITSORT_ERR_HIP;
+  (void)hipFree(ws);
+  return rc;
+}
+
+int bitsort_debug_bitmap_u32(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32_t* bitmap,
+                             bitsort_stream_t stream) {
+  return debug_run(keys, n, range_bits, kDumpBitmap, bitmap, nullptr, stream);
+}
+
+int bitsort_debug_prefix_u32(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint64_t* prefix,
+                             bitsort_stream_t stream) {
+  return debug_run(keys, n, range_bits, kDumpPrefix, nullptr, prefix, stream);
+}
+
+int bitsort_batch_u32(const uint32_t* keys, const uint64_t* offsets, uint32_t num_segments,
+                      const uint8_t* range_bits, uint32_t* out, uint64_t max_keys, bitsort_stream_t stream) {
+  if (num_segments == 0 || num_segments > BITSORT_BATCH_MAX_SEGMENTS) return BITSORT_ERR_INVALID_ARG;
+  if (keys == nullptr || offsets == nullptr || range_bits == nullptr || out == nullptr) return BITSORT_ERR_INVALID_ARG;
+  if (max_keys >= (1ull << 40)) return BITSORT_ERR_TOO_LARGE;
+  {
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(keys), a1 = a0 + 4 * max_keys;
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(out), b1 = b0 + 4 * max_keys;
+    if (max_keys > 0 && a0 < b1 && b0 < a1) return BITSORT_ERR_INVALID_ARG;
+  }
+  int rc = init_kernels();
+  if (rc != BITSORT_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint32_t sbb = kBatchSliceBits;
+  const uint64_t max_items = static_cast<uint64_t>(num_segments) << (kMaxBatchRangeBits - sbb);
+  const size_t off_status = kHeaderBytes;
+  const size_t off_items = align256(off_status + sizeof(SegStatus) * num_segments);
+  const size_t bytes = align256(off_items + sizeof(uint2) * max_items);
+  std::lock_guard<std::mutex> lock(g_mu);
+  StreamCtx& c = ctx_for(stream);
+  rc = grow(&c.batch_ws, &c.batch_bytes, bytes, s);
+  if (rc != BITSORT_OK) return rc;
+  c.batch_segments = num_segments;
+  char* base = static_cast<char*>(c.batch_ws);
+  uint32_t* counter = reinterpret_cast<uint32_t*>(base);
+  SegStatus* st = reinterpret_cast<SegStatus*>(base + off_status);
+  uint2* items = reinterpret_cast<uint2*>(base + off_items);
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, s, offsets, range_bits, num_segments, max_keys, sbb,
+                     items, counter, st);
+  rc = launch_status();
+  if (rc != BITSORT_OK) return rc;
+  const uint32_t stage_cap = stage_cap_for(sbb);
+  const size_t lds = slice_lds_bytes(sbb, stage_cap);
+  int cus = 256;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const uint64_t grid = std::min<uint64_t>(static_cast<uint64_t>(cus), max_items);
+  hipLaunchKernelGGL(k_batch_run<kBatchBlock>, dim3(static_cast<uint32_t>(grid)), dim3(kBatchBlock), lds, s, keys,
+                     offsets, range_bits, sbb, stage_cap, items, counter, out, st);
+  return launch_status();
+}
+
+int bitsort_batch_status(bitsort_stream_t stream, bitsort_status_t* status, uint32_t num_segments) {
+  if (status == nullptr) return BITSORT_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    StreamCtx& c = ctx_for(stream);
+    if (c.batch_ws == nullptr || num_segments > c.batch_segments) return BITSORT_ERR_INVALID_ARG;
+    ws = c.batch_ws;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return BITSORT_ERR_HIP;
+  static_assert(sizeof(SegStatus) == sizeof(bitsort_status_t), "status layouts must match");
+  if (num_segments == 0) return BITSORT_OK;
+  if (hipMemcpy(status, static_cast<char*>(ws) + kHeaderBytes, sizeof(SegStatus) * num_segments,
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return BITSORT_ERR_HIP;
+  return BITSORT_OK;
+}
+
+int bitsort_set_tuning(uint32_t slice_bits, uint32_t tile_log2) {
+  if (slice_bits != 0 && (slice_bits < kMinSliceBits || slice_bits > kMaxSliceBits)) return BITSORT_ERR_INVALID_ARG;
+  if (tile_log2 != 0 && (tile_log2 < 12 || tile_log2 > 14)) return BITSORT_ERR_INVALID_ARG;
+  g_tune_sb.store(slice_bits);
+  g_tune_tile.store(tile_log2);
+  return BITSORT_OK;
+}
+
+int bitsort_plan_info(uint64_t n, uint32_t range_bits, uint32_t* slice_bits, uint32_t* tile_log2,
+                      uint32_t* buckets) {
+  if (range_bits > 32 || slice_bits == nullptr || tile_log2 == nullptr || buckets == nullptr)
+    return BITSORT_ERR_INVALID_ARG;
+  Plan p;
+  make_plan(n, range_bits, &p);
+  *slice_bits = p.sb;
+  *tile_log2 = p.direct ? 0 : p.tile_log2;
+  *buckets = p.nb;
+  return BITSORT_OK;
+}
+
+}  // extern "C"

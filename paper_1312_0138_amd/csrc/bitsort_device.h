@@ -1,0 +1,120 @@
+// bitsort_device.h -- wavefront / block primitives for gfx950 (wave64).
+//
+// Everything here is device code used by the kernels in bitsort.hip.  The
+// prefix sums count set bits (Example 6 of Section III of the paper: the
+// number of ones in a word) and combine them across lanes with ballot and
+// mbcnt, the cross-lane primitives of the CDNA ISA.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace bitsort_dev {
+
+constexpr uint32_t kWave = 64;
+
+// Status block kept at the start of every workspace (layout of
+// bitsort_status_t followed by private counters).
+struct Status {
+  uint32_t flags;   // BITSORT_STATUS_* bits
+  uint32_t done;    // blocks finished (last-block detection)
+  uint64_t count;   // keys written
+};
+
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Values read from LDS or memory are per-lane as far as the compiler knows.
+// Any such value that decides a branch or loop around a barrier or a
+// cross-lane operation goes through uniform() first: it then lives in a
+// scalar register and the branch is a scalar one, so every wave takes it the
+// same way and executes the same barriers.
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t uniform(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Number of set bits of `m` in lanes below the calling lane.
+__device__ __forceinline__ uint32_t count_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+}
+
+// Exclusive wave prefix of c in [0, 63] built from six ballots (one per bit
+// plane of c) and mbcnt; *total receives the wave's sum.
+__device__ __forceinline__ uint32_t wave_prefix_small(uint32_t c, uint32_t* total) {
+  uint32_t p = 0, t = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 6; ++k) {
+    const uint64_t m = __ballot((c >> k) & 1u);
+    p += count_below(m) << k;
+    t += static_cast<uint32_t>(__popcll(m)) << k;
+  }
+  *total = t;
+  return p;
+}
+
+// Inclusive wave scan of arbitrary u32 values (Kogge-Stone over lanes).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (uint32_t d = 1; d < kWave; d <<= 1) {
+    const uint32_t y = __shfl_up(v, d, kWave);
+    if (lane >= d) v += y;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (uint32_t d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+// Exclusive block scan of one u32 per thread.  `scratch` holds BLOCK/64
+// words of LDS.  Contains two barriers; every thread must call it.
+template <int BLOCK>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* scratch, uint32_t* total) {
+  constexpr uint32_t kWaves = BLOCK / kWave;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t wave = threadIdx.x / kWave;
+  const uint32_t inc = wave_incl_scan(v);
+  if (lane == kWave - 1) scratch[wave] = inc;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kWaves; ++i) {
+    const uint32_t s = scratch[i];
+    base += (i < wave) ? s : 0u;
+    tot += s;
+  }
+  __syncthreads();
+  *total = uniform(tot);
+  return base + inc - v;
+}
+
+// Block sum of one u64 per thread; `scratch` holds BLOCK/64 u64 of LDS.
+template <int BLOCK>
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* scratch) {
+  constexpr uint32_t kWaves = BLOCK / kWave;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t wave = threadIdx.x / kWave;
+  v = wave_sum_u64(v);
+  if (lane == 0) scratch[wave] = v;
+  __syncthreads();
+  uint64_t tot = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kWaves; ++i) tot += scratch[i];
+  __syncthreads();
+  return uniform(tot);
+}
+
+__device__ __forceinline__ uint32_t atomic_load_flags(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace bitsort_dev

@@ -1,0 +1,245 @@
+"""Parity of the HIP plain path (bitsort_u32) with the CPU oracle.
+
+Every comparison is element by element (integers: bit-exact).  Inputs come
+from the seeded host generators in ``paper_1312_0138_amd.inputs``; the oracle
+never sees a value produced by the HIP path.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import require_gpu, to_dev, to_np
+from paper_1312_0138_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SENTINEL = 0xDEADBEEF
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+@pytest.fixture(scope="module")
+def o():
+    return oracle.default()
+
+
+def _gpu_sort(keys_np, rb, out_init=None):
+    import torch
+    import paper_1312_0138_amd as bs
+    k = to_dev(keys_np)
+    out = to_dev(out_init) if out_init is not None else torch.empty_like(k)
+    bs.sort(k, rb, out)
+    st = bs.status()
+    return to_np(out), st
+
+
+# (n, range_bits): both paths, word and tile boundaries, ragged tails.
+SIZES = [
+    (1, 0), (1, 1), (2, 1), (3, 2), (16, 4), (17, 5), (32, 5), (33, 6), (700, 10), (1024, 10),
+    (5000, 13), (8192, 20), (8193, 20), (9000, 14), (16384, 14), (20000, 16), (65536, 16),
+    (100_000, 20), (1 << 20, 20), (4097, 24), (16385, 24), (300_001, 24), (1_000_000, 24),
+    (50_000, 32), (1 << 18, 28), (123_457, 31), ((1 << 22) + 1, 24), (3 << 20, 22),
+]
+
+
+@pytest.mark.parametrize("n,rb", SIZES)
+def test_parity_sizes(o, n, rb):
+    keys = inputs.distinct_uniform(n, rb, inputs.config_seed(100 + rb, n))
+    want, flags, _ = o.bitmap_sort(keys, rb)
+    assert flags == 0
+    got, st = _gpu_sort(keys, rb)
+    assert st.flags == 0 and st.count == n
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("rep", [0, 1, 2])
+def test_parity_config_small(o, rep):
+    """10^6 distinct keys from [0, 2^24), three seeds."""
+    keys = inputs.distinct_uniform(1_000_000, 24, inputs.config_seed(1, rep))
+    want, _, _ = o.bitmap_sort(keys, 24)
+    got, st = _gpu_sort(keys, 24)
+    assert st.flags == 0 and st.count == keys.size
+    np.testing.assert_array_equal(got, want)
+
+
+def test_parity_config_large_uniform(o):
+    """2^26 distinct keys from [0, 2^28), full size."""
+    keys = inputs.distinct_uniform(1 << 26, 28, inputs.config_seed(2, 0))
+    want, _, _ = o.bitmap_sort(keys, 28)
+    got, st = _gpu_sort(keys, 28)
+    assert st.flags == 0 and st.count == keys.size
+    np.testing.assert_array_equal(got, want)
+
+
+def test_parity_clustered(o):
+    """Gaussian-cluster keys (64 clusters, sigma 2^16) in [0, 2^28)."""
+    keys = inputs.clustered(1 << 22, 28, inputs.config_seed(2, 1))
+    want, _, _ = o.bitmap_sort(keys, 28)
+    got, st = _gpu_sort(keys, 28)
+    assert st.flags == 0 and st.count == keys.size
+    np.testing.assert_array_equal(got, want)
+
+
+def test_dense_permutation_is_identity():
+    """A permutation of all of [0, 2^28) sorts to 0, 1, ..., 2^28-1."""
+    import torch
+    import paper_1312_0138_amd as bs
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    k = torch.randperm(1 << 28, device="cuda", dtype=torch.int64, generator=g).to(torch.int32)
+    out = torch.empty_like(k)
+    bs.sort(k, 28, out)
+    st = bs.status()
+    assert st.flags == 0 and st.count == 1 << 28
+    ref = torch.arange(1 << 28, device="cuda", dtype=torch.int32)
+    assert torch.equal(out, ref)
+
+
+def test_parity_sparse_full_range(o):
+    """2^24 distinct keys over all of [0, 2^32)."""
+    keys = inputs.distinct_uniform(1 << 24, 32, inputs.config_seed(3, 1))
+    want, _, _ = o.bitmap_sort(keys, 32)
+    got, st = _gpu_sort(keys, 32)
+    assert st.flags == 0 and st.count == keys.size
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("n,rb", [(3000, 12), (1 << 20, 20), (1_000_000, 24), (40_000, 27)])
+def test_mark_step_matches_oracle_bitmap(o, n, rb):
+    import paper_1312_0138_amd as bs
+    keys = inputs.distinct_uniform(n, rb, 77)
+    want, _ = o.bitmap_build(keys, rb)
+    got = to_np(bs.debug_bitmap(to_dev(keys), rb))
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("n,rb", [(3000, 12), (1 << 20, 20), (1_000_000, 24)])
+def test_scan_step_matches_oracle_prefix(o, n, rb):
+    import paper_1312_0138_amd as bs
+    keys = inputs.distinct_uniform(n, rb, 78)
+    words, _ = o.bitmap_build(keys, rb)
+    want = o.bitmap_scan(words)[:-1]
+    got = bs.debug_prefix(to_dev(keys), rb).cpu().numpy().astype(np.uint64)
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("n,rb", [(500, 12), (200_000, 24), (60_000, 32)])
+def test_out_of_range_keys_dropped(o, n, rb):
+    keys = inputs.distinct_uniform(n, rb + 1 if rb < 32 else 32, 5)
+    want, flags, _ = o.bitmap_sort(keys, rb)
+    init = np.full(n, SENTINEL, dtype=np.uint32)
+    got, st = _gpu_sort(keys, rb, out_init=init)
+    if rb < 32:
+        assert flags & oracle.FLAG_OUT_OF_RANGE
+        assert st.flags == 1
+    else:
+        assert st.flags == 0
+    d = want.size
+    assert st.count == d
+    np.testing.assert_array_equal(got[:d], want)
+    assert np.all(got[d:] == SENTINEL)
+
+
+@pytest.mark.parametrize("n,rb", [(400, 12), (300_000, 24), (5000, 20)])
+def test_duplicates_collapse(o, n, rb):
+    base = inputs.distinct_uniform(n, rb, 9)
+    rng = np.random.default_rng(1)
+    keys = base.copy()
+    dup_at = rng.choice(n, size=max(1, n // 10), replace=False)
+    keys[dup_at] = base[rng.integers(0, n, size=dup_at.size)]
+    want, flags, _ = o.bitmap_sort(keys, rb)
+    assert flags & oracle.FLAG_DUPLICATE
+    got, st = _gpu_sort(keys, rb)
+    assert st.flags & 2 and st.count == want.size
+    np.testing.assert_array_equal(got[: want.size], want)
+
+
+def test_in_place_and_misaligned(o):
+    import torch
+    import paper_1312_0138_amd as bs
+    keys = inputs.distinct_uniform(500_000, 24, 11)
+    want, _, _ = o.bitmap_sort(keys, 24)
+    k = to_dev(keys)
+    bs.sort(k, 24, k)  # out == keys
+    np.testing.assert_array_equal(to_np(k), want)
+    buf = to_dev(np.concatenate([[7], keys]))
+    view = buf[1:]  # 4-byte aligned, not 16-byte aligned
+    out = torch.empty_like(view)
+    bs.sort(view, 24, out)
+    np.testing.assert_array_equal(to_np(out), want)
+
+
+def test_rejects_partial_overlap_and_bad_sizes():
+    import torch
+    import paper_1312_0138_amd as bs
+    buf = torch.zeros(101, dtype=torch.int32, device="cuda")
+    with pytest.raises(bs.BitsortError):
+        bs.sort(buf[:100], 10, buf[1:])
+    with pytest.raises(bs.BitsortError):
+        bs.sort(buf[:100], 6)  # 100 keys cannot be distinct below 64
+    with pytest.raises(bs.BitsortError):
+        bs.sort(buf[:100], 33)
+
+
+def test_empty_input():
+    import torch
+    import paper_1312_0138_amd as bs
+    k = torch.empty(0, dtype=torch.int32, device="cuda")
+    bs.sort(k, 20)
+    st = bs.status()
+    assert st.flags == 0 and st.count == 0
+
+
+def test_deterministic_repeats():
+    import torch
+    import paper_1312_0138_amd as bs
+    keys = to_dev(inputs.distinct_uniform(1 << 22, 26, 13))
+    ref = bs.sort(keys, 26).clone()
+    for _ in range(5):
+        assert torch.equal(bs.sort(keys, 26), ref)
+
+
+def test_side_stream_and_workspace_variant(o):
+    import torch
+    import paper_1312_0138_amd as bs
+    keys = inputs.distinct_uniform(2_000_000, 25, 17)
+    want, _, _ = o.bitmap_sort(keys, 25)
+    k = to_dev(keys)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out = bs.sort(k, 25)
+        st = bs.status(s)
+    assert st.count == keys.size
+    np.testing.assert_array_equal(to_np(out), want)
+    ws = torch.empty(bs.workspace_bytes(keys.size, 25), dtype=torch.uint8, device="cuda")
+    out2 = bs.sort_ws(k, 25, ws)
+    st2 = bs.workspace_status(ws)
+    assert st2.flags == 0 and st2.count == keys.size
+    np.testing.assert_array_equal(to_np(out2), want)
+
+
+@pytest.mark.parametrize("sb,tl", [(10, 12), (14, 13), (18, 14), (20, 12), (16, 14)])
+def test_tuning_knobs_keep_results(o, sb, tl):
+    import paper_1312_0138_amd as bs
+    keys = inputs.distinct_uniform(700_001, 24, 19)
+    want, _, _ = o.bitmap_sort(keys, 24)
+    bs.set_tuning(sb, tl)
+    try:
+        got, st = _gpu_sort(keys, 24)
+    finally:
+        bs.set_tuning(0, 0)
+    assert st.count == keys.size
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("rb,first,count", [(0, 0, 1), (1, 0, 2), (5, 3, 20), (7, 0, 128), (16, 100, 5000),
+                                            (24, 12345, 100_000), (31, 1 << 30, 70_000), (32, 0, 100_000)])
+def test_device_generator_matches_host(rb, first, count):
+    import paper_1312_0138_amd as bs
+    seed = 0xABCDEF + rb
+    got = to_np(bs.generate(count, rb, seed, first=first))
+    want = inputs.keyed_permutation(np.arange(first, first + count, dtype=np.uint64), rb, seed)
+    np.testing.assert_array_equal(got, want)
