@@ -1,0 +1,334 @@
+#!/usr/bin/env python3
+"""Benchmark of the bitmap sort on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one bitsort_u32 call (partition + slice kernels) over one array
+already resident in HBM; inputs rotate through a pool of device buffers whose
+total exceeds the 256 MB Infinity Cache.  Prints one JSON line with the
+whole-job throughput (Gkeys/s), the dominant kernel's roofline against the
+8 TB/s HBM3E peak (its duration measured with HIP events on its own stream),
+and the CPU oracle timed on this host's cores as a reported baseline.
+
+Workloads (default: plain-uniform):
+  plain-uniform   2^26 distinct keys uniform without replacement in [0, 2^28)
+  plain-small     10^6 distinct keys in [0, 2^24)
+  plain-clustered keys from 64 Gaussian clusters (sigma 2^16) in [0, 2^28)
+  plain-dense     a permutation of all of [0, 2^28)
+  plain-sparse    2^24 distinct keys in [0, 2^32)
+  batch           4096 arrays, sizes log-uniform in [256, 2^20], range the
+                  power of two >= 4n: one batched launch vs 4096 plain launches
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "sorted Gkeys/s and % of HBM roofline at 1 GPU; batched vs per-array plain, p99"
+HBM_PEAK_GBPS = 8000.0
+MALL_BYTES = 256 << 20
+
+PLAIN = {
+    "plain-uniform": dict(n=1 << 26, rb=28, cfg=2, desc="2^26 distinct uint32 keys uniform in [0, 2^28), 32 MiB bit-vector"),
+    "plain-small": dict(n=1_000_000, rb=24, cfg=1, desc="10^6 distinct uint32 keys uniform in [0, 2^24), 2 MiB bit-vector"),
+    "plain-clustered": dict(n=None, rb=28, cfg=2, desc="64 Gaussian clusters (sigma 2^16) in [0, 2^28), 2^26 draws de-duplicated"),
+    "plain-dense": dict(n=1 << 28, rb=28, cfg=3, desc="permutation of all of [0, 2^28)"),
+    "plain-sparse": dict(n=1 << 24, rb=32, cfg=3, desc="2^24 distinct uint32 keys uniform in [0, 2^32), 512 MiB bit-vector"),
+}
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1312_0138_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(n: int, rb: int) -> dict:
+    """The method's bytes: keys in (4n), one pass over the R-bit bit-vector
+    (R/8), keys out (4n).  Attributed per kernel: k_partition reads the keys;
+    k_slice owns the bit-vector pass and writes the keys out."""
+    r8 = (1 << rb) // 8
+    return {"k_partition": 4 * n, "k_slice": r8 + 4 * n, "k_direct": 4 * n + r8 + 4 * n,
+            "path": 4 * n + r8 + 4 * n}
+
+
+def read_traffic(kernel: str, workload: str, digest: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_digest") != digest:
+        return None
+    try:
+        return int(float(vals["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(keys_host, rb: int, budget_s: float = 12.0, max_reps: int = 5):
+    """The oracle, single-threaded, timed on the host: (Gkeys/s, reps, out)."""
+    import oracle
+    o = oracle.default()
+    times, out = [], None
+    t_start = time.perf_counter()
+    for _ in range(max_reps):
+        t0 = time.perf_counter()
+        out, _, _ = o.bitmap_sort(keys_host, rb)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start > budget_s:
+            break
+    med = statistics.median(times)
+    return keys_host.size / med / 1e9, len(times), med, out
+
+
+def make_plain_inputs(bs, torch, spec, workload, pool):
+    from paper_1312_0138_amd import inputs
+    n, rb, cfg = spec["n"], spec["rb"], spec["cfg"]
+    bufs = []
+    if workload == "plain-clustered":
+        host = inputs.clustered(1 << 26, rb, inputs.config_seed(cfg, 1))
+        n = host.size
+        t = torch.from_numpy(host.view("int32")).cuda()
+        bufs = [t] + [t.clone() for _ in range(pool - 1)]
+        return bufs, n
+    for rep in range(pool):
+        t = torch.empty(n, dtype=torch.int32, device="cuda")
+        bs.generate(n, rb, inputs.config_seed(cfg, rep), out=t)
+        bufs.append(t)
+    return bufs, n
+
+
+def host_input(spec, workload, n):
+    from paper_1312_0138_amd import inputs
+    rb, cfg = spec["rb"], spec["cfg"]
+    if workload == "plain-clustered":
+        return inputs.clustered(1 << 26, rb, inputs.config_seed(cfg, 1))
+    return inputs.distinct_uniform(n, rb, inputs.config_seed(cfg, 0))
+
+
+def bench_plain(args, workload):
+    import numpy as np
+    import torch
+
+    import paper_1312_0138_amd as bs
+    from paper_1312_0138_amd import _lib
+
+    spec = PLAIN[workload]
+    rb = spec["rb"]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    pool = args.pool
+    if pool == 0:
+        per = 4 * (spec["n"] or (1 << 26))
+        pool = max(2, min(128, -(-2 * MALL_BYTES // per)))
+    bufs, n = make_plain_inputs(bs, torch, spec, workload, pool)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    plan = bs.plan_info(n, rb)
+
+    for i in range(args.warmup):
+        bs.sort(bufs[i % len(bufs)], rb, out)
+    torch.cuda.synchronize()
+
+    _lib.check(_lib.bitsort_profile_reset(), "profile_reset")
+    _lib.check(_lib.bitsort_profile_enable(True), "profile_enable")
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for i in range(args.steps):
+        starts[i].record(stream)
+        bs.sort(bufs[i % len(bufs)], rb, out)
+        ends[i].record(stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    _lib.check(_lib.bitsort_profile_enable(False), "profile_enable")
+    rc, prof = _lib.bitsort_profile_read()
+    _lib.check(rc, "profile_read")
+    total_ms = t0.elapsed_time(t1)
+    step_ms = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
+    p50 = step_ms[len(step_ms) // 2]
+    p99 = step_ms[min(len(step_ms) - 1, int(round(0.99 * (len(step_ms) - 1))))]
+    st = bs.status()
+    assert st.flags == 0 and st.count == n, f"device status flags={st.flags} count={st.count}"
+
+    ms_per_step = total_ms / args.steps
+    value = n / (ms_per_step / 1e3) / 1e9
+    ab = algorithmic_bytes(n, rb)
+    kernels = {k: {"launches": int(l), "avg_us": 1e3 * ms / max(l, 1)} for k, (l, ms) in prof.items()}
+    dom = max(prof, key=lambda k: prof[k][1])
+    dom_avg_s = prof[dom][1] / prof[dom][0] / 1e3
+    digest = source_digest()
+    achieved = ab[dom] / dom_avg_s / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": read_traffic(dom, workload, digest), "algorithmic_bytes": ab[dom]}
+    path_gbps = ab["path"] / (ms_per_step / 1e3) / 1e9
+    result = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": workload, "description": spec["desc"], "n": n, "range_bits": rb,
+                   "input_pool": len(bufs), "slice_bits": plan["slice_bits"], "tile_log2": plan["tile_log2"],
+                   "slices": plan["buckets"]},
+        "p50_ms": round(p50, 5), "p99_ms": round(p99, 5),
+        "roofline": roofline,
+        "roofline_path": {"achieved": round(path_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                          "frac": round(path_gbps / HBM_PEAK_GBPS, 4), "algorithmic_bytes": ab["path"]},
+        "kernels": kernels, "source_digest": digest,
+    }
+    if not args.no_cpu_baseline:
+        keys_host = host_input(spec, workload, n)
+        gk, reps, med, want = cpu_baseline(keys_host, rb)
+        # the GPU result for the same input must equal the oracle's
+        check_in = torch.from_numpy(keys_host.view(np.int32)).cuda()
+        got = bs.sort(check_in, rb).cpu().numpy().view(np.uint32)
+        if not np.array_equal(got, want):
+            print(json.dumps({"error": "GPU output differs from the CPU oracle", "workload": workload}))
+            sys.exit(3)
+        result["cpu_baseline"] = {"value": round(gk, 4), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+                                  "sample": f"full {workload} input (n={n}), {reps} repetition(s), "
+                                            f"median {med:.3f} s per sort; single-threaded C oracle",
+                                  "host_cores": os.cpu_count()}
+        result["verified_against_oracle"] = True
+    return result
+
+
+def bench_batch(args):
+    import numpy as np
+    import torch
+
+    import paper_1312_0138_amd as bs
+    from paper_1312_0138_amd import _lib, inputs
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    count, seed = 4096, inputs.config_seed(4, 0)
+    sizes = inputs.log_uniform_sizes(count, 256, 1 << 20, seed)
+    rbits = np.array([inputs.range_bits_for(n) for n in sizes], dtype=np.uint8)
+    offsets = np.zeros(count + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(sizes)
+    total = int(offsets[-1])
+    keys = torch.empty(total, dtype=torch.int32, device="cuda")
+    for i in range(count):
+        lo, hi = int(offsets[i]), int(offsets[i + 1])
+        bs.generate(hi - lo, int(rbits[i]), inputs.segment_seed(seed, i), out=keys[lo:hi])
+    off_d = torch.from_numpy(offsets.astype(np.int64)).cuda()
+    rb_d = torch.from_numpy(rbits).cuda()
+    out_b = torch.empty_like(keys)
+    out_p = torch.empty_like(keys)
+    views = [(keys[int(offsets[i]):int(offsets[i + 1])], out_p[int(offsets[i]):int(offsets[i + 1])], int(rbits[i]))
+             for i in range(count)]
+
+    def run_batch():
+        bs.sort_batch(keys, off_d, rb_d, out_b)
+
+    def run_plain():
+        for k, o, rb in views:
+            bs.sort(k, rb, o)
+
+    for _ in range(args.warmup):
+        run_batch()
+        run_plain()
+    torch.cuda.synchronize()
+    res = {}
+    for name, fn in (("batched", run_batch), ("plain_loop", run_plain)):
+        times = []
+        for _ in range(max(3, args.steps // 10)):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        times.sort()
+        med = times[len(times) // 2]
+        res[name] = {"median_ms": round(med, 4), "p99_ms": round(times[-1], 4),
+                     "gkeys_per_s": round(total / (med / 1e3) / 1e9, 3)}
+    flags, counts = bs.batch_status(count)
+    assert not flags.any() and np.array_equal(counts, sizes.astype(np.uint64))
+    same = torch.equal(out_b, out_p)
+    ab = sum(4 * int(n) + (1 << int(r)) // 8 + 4 * int(n) for n, r in zip(sizes, rbits))
+    med_s = res["batched"]["median_ms"] / 1e3
+    return {
+        "metric": METRIC, "value": res["batched"]["gkeys_per_s"], "unit": "Gkeys/s", "n_gpus": 1,
+        "steps": max(3, args.steps // 10), "warmup": args.warmup, "ms_per_step": res["batched"]["median_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "batch", "segments": count, "total_keys": total,
+                   "sizes": "log-uniform in [256, 2^20]", "range": "next power of two >= 4n"},
+        "batched": res["batched"], "plain_loop": res["plain_loop"],
+        "batched_over_plain": round(res["plain_loop"]["median_ms"] / res["batched"]["median_ms"], 3),
+        "identical_results": bool(same),
+        "roofline_path": {"achieved": round(ab / med_s / 1e9, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                          "frac": round(ab / med_s / 1e9 / HBM_PEAK_GBPS, 4), "algorithmic_bytes": ab},
+    }
+
+
+def copy_calibration(args):
+    """A plain device copy of known size (1 GiB read + 1 GiB written per
+    launch), for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters and as
+    the practical bandwidth ceiling."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(7)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    reps = max(3, args.steps // 10)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return {"workload": "copy-calibration", "bytes_read_per_launch": nbytes, "bytes_written_per_launch": nbytes,
+            "ms_per_copy": round(ms, 4), "copy_GBps": round(2 * nbytes / (ms / 1e3) / 1e9, 1), "launches": reps + 2}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="plain-uniform", choices=sorted(PLAIN) + ["batch", "copy-calibration"])
+    ap.add_argument("--pool", type=int, default=0, help="input buffers to rotate through (0: auto)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "batch":
+        result = bench_batch(args)
+    elif args.workload == "copy-calibration":
+        result = copy_calibration(args)
+    else:
+        result = bench_plain(args, args.workload)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -173,6 +173,24 @@ int bitsort_set_tuning(uint32_t slice_bits, uint32_t tile_log2);
 int bitsort_plan_info(uint64_t n, uint32_t range_bits, uint32_t *slice_bits, uint32_t *tile_log2,
                       uint32_t *buckets);
 
+/*
+ * Kernel timing for benchmarks.  While enabled, every kernel the library
+ * launches is bracketed by two HIP events recorded on the launch's own
+ * stream.  bitsort_profile_read() waits for those events and returns, per
+ * kernel name, the number of launches and their summed duration since the
+ * last reset (at most max_entries entries; *n_entries receives the count).
+ * Enabling costs two event records per kernel launch.
+ */
+typedef struct bitsort_profile_entry {
+    char kernel[32];      /* k_partition, k_slice, k_direct, k_batch_plan, k_batch_run */
+    uint64_t launches;
+    double total_ms;
+} bitsort_profile_entry_t;
+
+int bitsort_profile_enable(int on);
+int bitsort_profile_reset(void);
+int bitsort_profile_read(bitsort_profile_entry_t *entries, int max_entries, int *n_entries);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,6 +34,10 @@ class Status(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("_pad", ctypes.c_uint32), ("count", ctypes.c_uint64)]
 
 
+class ProfileEntry(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
+
+
 _c = ctypes
 _vp = ctypes.c_void_p
 _u32 = ctypes.c_uint32
@@ -53,6 +57,9 @@ _SIGS = {
     "bitsort_debug_prefix_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
     "bitsort_set_tuning": (_c.c_int, [_u32, _u32]),
     "bitsort_plan_info": (_c.c_int, [_u64, _u32, _c.POINTER(_u32), _c.POINTER(_u32), _c.POINTER(_u32)]),
+    "bitsort_profile_enable": (_c.c_int, [_c.c_int]),
+    "bitsort_profile_reset": (_c.c_int, []),
+    "bitsort_profile_read": (_c.c_int, [_c.POINTER(ProfileEntry), _c.c_int, _c.POINTER(_c.c_int)]),
 }
 
 _lib = None
@@ -152,3 +159,19 @@ def bitsort_plan_info(n: int, range_bits: int):
     sb, tl, nb = _u32(), _u32(), _u32()
     rc = lib().bitsort_plan_info(n, range_bits, ctypes.byref(sb), ctypes.byref(tl), ctypes.byref(nb))
     return rc, sb.value, tl.value, nb.value
+
+
+def bitsort_profile_enable(on: bool) -> int:
+    return lib().bitsort_profile_enable(1 if on else 0)
+
+
+def bitsort_profile_reset() -> int:
+    return lib().bitsort_profile_reset()
+
+
+def bitsort_profile_read():
+    """-> (rc, {kernel: (launches, total_ms)})."""
+    arr = (ProfileEntry * 16)()
+    n = ctypes.c_int()
+    rc = lib().bitsort_profile_read(arr, 16, ctypes.byref(n))
+    return rc, {arr[i].kernel.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(n.value, 16))}

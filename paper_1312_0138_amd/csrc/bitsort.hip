@@ -46,6 +46,7 @@
 #include <map>
 #include <mutex>
 #include <utility>
+#include <vector>
 
 #include "bitsort.h"
 #include "bitsort_device.h"
@@ -59,7 +60,7 @@ constexpr uint32_t kMaxSliceBits = 20;        // 2^20 bits = 128 KiB of LDS
 constexpr uint32_t kMinSliceBits = 10;
 constexpr uint32_t kMaxBucketsLog2 = 12;      // partition fan-out <= 4096
 constexpr uint32_t kSliceBlock = 1024;
-constexpr uint32_t kSliceUnroll = 8;
+constexpr uint32_t kSliceUnroll = 32;
 constexpr uint32_t kDirectBlock = 1024;
 constexpr uint64_t kDirectMaxN = 8192;        // single-workgroup path below this
 constexpr uint32_t kHeaderBytes = 256;        // status + scratch header in LDS / workspace
@@ -75,80 +76,142 @@ __host__ __device__ constexpr uint32_t round_up4(uint32_t x) { return (x + 3u) &
 // Scan and emit one LDS slice (Example 6 per word, then Example 1 per bit).
 //
 // slice[0 .. slice_words) holds the marked bits of keys key_base + 32*w + b.
-// Words are taken BLOCK at a time (one per thread): each thread counts the
-// ones of its word, the block forms the exclusive prefix p (ballot bit planes
-// + per-wave sums in LDS), and every set bit of the word is written to
-// stage[p + j - lo] for the window [lo, lo + stage_cap) of the chunk's output;
-// the window is then copied to out[out_base + done + lo ...] with contiguous
-// stores.  Returns the number of set bits (uniform).  Every thread calls it.
+// Count pass: wave v owns the word range [v*per, (v+1)*per) and sums the
+// ones in it; one barrier turns the per-wave sums into each wave's output
+// offset.  Emit pass, with no further block barrier: the wave walks its range
+// 64 words at a time (lane l <-> word w0 + l), forms the exclusive prefix p of
+// the per-word counts with ballot bit planes, and writes word w's keys
+// key_base + 32w + ctz(x) (clearing the lowest set bit each time) to
+// out[D + p ...].  Three shapes:
+//   - no word has more than one key: each key goes straight to its rank
+//     among the nonzero lanes (one store for the whole group);
+//   - all 64 words full: 2048 consecutive keys, stored as a sequence;
+//   - otherwise the keys are staged in the wave's own LDS window at their
+//     prefix positions (offset by the destination's 16-byte phase) and copied
+//     out with 16-byte stores, in as many windows as the group needs.
+// Returns the number of set bits (uniform).  Every thread of the block calls
+// it.  mode != kEmit writes the bit-vector or the per-word prefix instead.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (uint32_t d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+// Copy ws[shift .. shift + m) to dst[0 .. m), where dst + e is 16-byte
+// aligned exactly when (shift + e) % 4 == 0.
+__device__ __forceinline__ void wave_copy_out(const uint32_t* ws, uint32_t shift, uint32_t* dst, uint32_t m) {
+  const uint32_t lane = lane_id();
+  uint32_t h = (4u - shift) & 3u;
+  if (h > m) h = m;
+  if (lane < h) dst[lane] = ws[shift + lane];
+  const uint32_t q = (m - h) >> 2;
+  const uint4* src4 = reinterpret_cast<const uint4*>(ws + shift + h);
+  uint4* dst4 = reinterpret_cast<uint4*>(dst + h);
+  for (uint32_t v = lane; v < q; v += kWave) dst4[v] = src4[v];
+  const uint32_t t0 = h + (q << 2);
+  if (t0 + lane < m) dst[t0 + lane] = ws[shift + t0 + lane];
+}
+
 template <int BLOCK>
 __device__ uint64_t scan_emit(const uint32_t* slice, uint32_t slice_words, uint32_t key_base,
                               uint32_t* stage, uint32_t stage_cap, uint32_t* scratch,
                               uint32_t* __restrict__ out, uint64_t out_base, int mode,
                               uint32_t* dbg_bitmap, uint64_t* dbg_prefix, uint64_t dbg_word0) {
   constexpr uint32_t kWaves = BLOCK / kWave;
-  const uint32_t tid = threadIdx.x;
-  const uint32_t lane = tid & (kWave - 1);
-  const uint32_t wave = tid / kWave;
-  uint64_t done = 0;
-  for (uint32_t w0 = 0; w0 < slice_words; w0 += BLOCK) {
-    const uint32_t w = w0 + tid;
-    const uint32_t x = (w < slice_words) ? slice[w] : 0u;
-    const uint32_t c = static_cast<uint32_t>(__popc(x));
-    uint32_t wt;
-    const uint32_t wp = wave_prefix_small(c, &wt);
-    if (lane == 0) scratch[wave] = wt;
-    __syncthreads();
-    uint32_t wb = 0, ct = 0;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t wave = threadIdx.x / kWave;
+  const uint32_t per = (slice_words + kWaves - 1) / kWaves;
+  const uint32_t w_lo = min(wave * per, slice_words), w_hi = min(w_lo + per, slice_words);
+
+  uint32_t cnt = 0;
+  for (uint32_t w = w_lo + lane; w < w_hi; w += kWave) cnt += static_cast<uint32_t>(__popc(slice[w]));
+  cnt = wave_sum_u32(cnt);
+  if (lane == 0) scratch[wave] = cnt;
+  __syncthreads();
+  uint64_t wbase = 0, total = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < kWaves; ++i) {
-      const uint32_t v = scratch[i];
-      wb += (i < wave) ? v : 0u;
-      ct += v;
+  for (uint32_t i = 0; i < kWaves; ++i) {
+    const uint32_t v = scratch[i];
+    wbase += (i < wave) ? v : 0u;
+    total += v;
+  }
+  total = uniform(total);
+  wbase = uniform(wbase);
+  __syncthreads();  // scratch is reused by the caller
+
+  const uint32_t wsw = (stage_cap / kWaves) & ~3u;  // this wave's LDS window, 16-byte aligned
+  uint32_t* ws = stage + wave * wsw;
+  const uint32_t win = wsw - 4u;
+  uint64_t D = out_base + wbase;
+  for (uint32_t w0 = w_lo; w0 < w_hi; w0 += kWave) {
+    const uint32_t w = w0 + lane;
+    const uint32_t x = (w < w_hi) ? slice[w] : 0u;
+    const uint32_t c = static_cast<uint32_t>(__popc(x));
+    if (mode == kEmit) {
+      const uint64_t nz = __ballot(c != 0u);
+      if (nz == 0) continue;
+      if (__ballot(c > 1u) == 0) {
+        if (c != 0u) out[D + count_below(nz)] = key_base + (w << 5) + static_cast<uint32_t>(__builtin_ctz(x));
+        D += static_cast<uint32_t>(__popcll(nz));
+        continue;
+      }
+      if (w0 + kWave <= w_hi && __ballot(x != 0xFFFFFFFFu) == 0) {
+        const uint32_t kb0 = key_base + (w0 << 5);
+#pragma unroll 8
+        for (uint32_t j = 0; j < 32; ++j) out[D + j * kWave + lane] = kb0 + j * kWave + lane;
+        D += 32u * kWave;
+        continue;
+      }
     }
-    ct = uniform(ct);
-    const uint32_t p = wb + wp;
+    uint32_t tot;
+    const uint32_t p = wave_prefix_small(c, &tot);
+    tot = uniform(tot);
     if (mode == kDumpBitmap) {
-      if (w < slice_words) dbg_bitmap[dbg_word0 + w] = x;
+      if (w < w_hi) dbg_bitmap[dbg_word0 + w] = x;
     } else if (mode == kDumpPrefix) {
-      if (w < slice_words) dbg_prefix[dbg_word0 + w] = out_base + done + p;
+      if (w < w_hi) dbg_prefix[dbg_word0 + w] = D + p;
     } else {
-      for (uint32_t lo = 0; lo < ct; lo += stage_cap) {
-        if (c != 0 && p < lo + stage_cap && p + c > lo) {
+      for (uint32_t lo = 0; lo < tot; lo += win) {
+        uint32_t* dst = out + D + lo;
+        const uint32_t shift = static_cast<uint32_t>((reinterpret_cast<uintptr_t>(dst) >> 2) & 3u);
+        if (c != 0u && p < lo + win && p + c > lo) {
           uint32_t y = x, pos = p;
           while (pos < lo) {  // drop the bits that belong to earlier windows
             y &= y - 1u;
             ++pos;
           }
           const uint32_t kb = key_base + (w << 5);
-          while (y != 0u && pos < lo + stage_cap) {
-            stage[pos - lo] = kb + static_cast<uint32_t>(__builtin_ctz(y));
+          while (y != 0u && pos < lo + win) {
+            ws[shift + pos - lo] = kb + static_cast<uint32_t>(__builtin_ctz(y));
             y &= y - 1u;
             ++pos;
           }
         }
-        __syncthreads();
-        const uint32_t m = min(stage_cap, ct - lo);
-        uint32_t* dst = out + out_base + done + lo;
-        for (uint32_t i = tid; i < m; i += BLOCK) dst[i] = stage[i];
-        __syncthreads();
+        wave_sync();
+        wave_copy_out(ws, shift, dst, min(win, tot - lo));
+        wave_sync();
       }
     }
-    __syncthreads();  // scratch is rewritten by the next chunk
-    done += ct;
+    D += tot;
   }
-  return done;
+  return total;
 }
 
 // One workgroup moves every slice's output left so that the slices' keys are
-// contiguous (only after a duplicate key made some slice write fewer keys
-// than its share).  binfo[2b] = where slice b wrote, binfo[2b+1] = how many.
+// contiguous (only after a duplicate key made some slice write fewer keys than
+// its share).  info[3b] = where slice b wrote, info[3b+1] = how many.
 template <int BLOCK>
-__device__ void compact_slices(uint32_t* out, const uint64_t* binfo, uint32_t nb) {
+__device__ void compact_slices(uint32_t* out, const uint64_t* info, uint32_t nb) {
   uint64_t dst = 0;
   for (uint32_t b = 0; b < nb; ++b) {
-    const uint64_t src = uniform(__hip_atomic_load(&binfo[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    const uint64_t cnt = uniform(__hip_atomic_load(&binfo[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const uint64_t src = uniform(info[3 * b]);
+    const uint64_t cnt = uniform(info[3 * b + 1]);
     if (src != dst) {
       for (uint64_t i0 = 0; i0 < cnt; i0 += BLOCK) {
         const uint64_t i = i0 + threadIdx.x;
@@ -171,8 +234,7 @@ template <int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t* __restrict__ keys, uint64_t n,
                                                      uint64_t range, uint32_t sb, uint32_t nb,
                                                      uint32_t* __restrict__ staging,
-                                                     uint32_t* __restrict__ table, Status* status,
-                                                     int vec_ok) {
+                                                     uint32_t* __restrict__ table, int vec_ok) {
   static_assert(ITEMS % 4 == 0, "ITEMS must be a multiple of 4");
   constexpr uint32_t T = BLOCK * ITEMS;
   extern __shared__ __align__(16) uint32_t lds[];
@@ -180,11 +242,6 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t* __restrict_
   uint32_t* hist = lds + 32;
   uint32_t* tk = lds + 32 + round_up4(nb);
   const uint32_t tid = threadIdx.x;
-  if (blockIdx.x == 0 && tid == 0) {
-    status->flags = 0;
-    status->done = 0;
-    status->count = 0;
-  }
   const uint64_t base = static_cast<uint64_t>(blockIdx.x) * T;
   const uint32_t cnt = static_cast<uint32_t>(min(static_cast<uint64_t>(T), n - base));
   for (uint32_t i = tid; i < nb; i += BLOCK) hist[i] = 0u;
@@ -257,16 +314,45 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Slice: mark (second half), scan and emit one slice b = blockIdx.x.
+// Slice: mark (second half), scan and emit one slice.
+//
+// Workgroups are handed out round-robin over the eight XCDs (blockIdx % 8),
+// so blockIdx is mapped to slices such that each XCD takes a contiguous run of
+// slices: the segments of neighbouring slices share cache lines at their
+// boundaries, and these are then read through the same L2.
 //
 // LDS: [scratch64 16 u64][scratch 32 words][slice 2^sb bits][stage].
 template <int BLOCK, int UNROLL>
+__device__ __forceinline__ void load_units(uint32_t u0, uint32_t utot, uint32_t upre, uint32_t s, uint32_t e,
+                                           uint32_t lane, uint32_t t0, uint32_t tile_keys,
+                                           const uint32_t* __restrict__ staging, uint32_t* kk, bool* vv) {
+#pragma unroll
+  for (int q = 0; q < UNROLL; ++q) {
+    const uint32_t u = u0 + q;
+    vv[q] = false;
+    kk[q] = 0u;
+    if (u < utot) {
+      // Owner of unit u: the last lane whose unit prefix is <= u.
+      const uint64_t m = __ballot(upre <= u);
+      const uint32_t j = static_cast<uint32_t>(__popcll(m)) - 1u;
+      const uint32_t sj = __builtin_amdgcn_readlane(s, j);
+      const uint32_t ej = __builtin_amdgcn_readlane(e, j);
+      const uint32_t pj = __builtin_amdgcn_readlane(upre, j);
+      const uint32_t idx = sj + (u - pj) * kWave + lane;
+      if (idx < ej) {
+        kk[q] = staging[static_cast<uint64_t>(t0 + j) * tile_keys + idx];
+        vv[q] = true;
+      }
+    }
+  }
+}
+
+template <int BLOCK, int UNROLL>
 __global__ __launch_bounds__(BLOCK) void k_slice(const uint32_t* __restrict__ staging,
                                                  const uint32_t* __restrict__ table, uint32_t nt,
-                                                 uint32_t tile_keys, uint64_t n, uint32_t sb,
-                                                 uint32_t nb, uint32_t stage_cap,
-                                                 uint32_t* __restrict__ out, Status* status,
-                                                 uint64_t* __restrict__ binfo, int mode,
+                                                 uint32_t tile_keys, uint32_t sb, uint32_t nb,
+                                                 uint32_t stage_cap, uint32_t* __restrict__ out,
+                                                 uint64_t* __restrict__ info, int mode,
                                                  uint32_t* dbg_bitmap, uint64_t* dbg_prefix) {
   constexpr uint32_t kWaves = BLOCK / kWave;
   extern __shared__ __align__(16) uint32_t lds[];
@@ -278,7 +364,9 @@ __global__ __launch_bounds__(BLOCK) void k_slice(const uint32_t* __restrict__ st
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & (kWave - 1);
   const uint32_t wave = tid / kWave;
-  const uint32_t b = blockIdx.x;
+  const uint32_t per8 = (nb + 7u) / 8u;
+  const uint32_t b = (blockIdx.x % 8u) * per8 + blockIdx.x / 8u;
+  if (b >= nb) return;  // padding block of the 8-way mapping
 
   for (uint32_t i = tid; i < slice_words; i += BLOCK) slice[i] = 0u;
   __syncthreads();
@@ -305,25 +393,7 @@ __global__ __launch_bounds__(BLOCK) void k_slice(const uint32_t* __restrict__ st
     for (uint32_t u0 = 0; u0 < utot; u0 += UNROLL) {
       uint32_t kk[UNROLL];
       bool vv[UNROLL];
-#pragma unroll
-      for (int q = 0; q < UNROLL; ++q) {
-        const uint32_t u = u0 + q;
-        vv[q] = false;
-        kk[q] = 0u;
-        if (u < utot) {
-          // Owner of unit u: the last lane whose unit prefix is <= u.
-          const uint64_t m = __ballot(upre <= u);
-          const uint32_t j = static_cast<uint32_t>(__popcll(m)) - 1u;
-          const uint32_t sj = __shfl(s, j, kWave);
-          const uint32_t ej = __shfl(e, j, kWave);
-          const uint32_t pj = __shfl(upre, j, kWave);
-          const uint32_t idx = sj + (u - pj) * kWave + lane;
-          if (idx < ej) {
-            kk[q] = staging[static_cast<uint64_t>(t0 + j) * tile_keys + idx];
-            vv[q] = true;
-          }
-        }
-      }
+      load_units<BLOCK, UNROLL>(u0, utot, upre, s, e, lane, t0, tile_keys, staging, kk, vv);
 #pragma unroll
       for (int q = 0; q < UNROLL; ++q)
         if (vv[q]) {
@@ -332,34 +402,44 @@ __global__ __launch_bounds__(BLOCK) void k_slice(const uint32_t* __restrict__ st
         }
     }
   }
-  const uint64_t base_b = block_sum_u64<BLOCK>(base_acc, scratch64);
+  const uint64_t base_b = block_sum_u64<BLOCK>(base_acc, scratch64);  // also orders the marks before the scan
   const uint64_t cnt_b = block_sum_u64<BLOCK>(cnt_acc, scratch64);
 
   const uint32_t key_base = b << sb;
   const uint64_t pop = scan_emit<BLOCK>(slice, slice_words, key_base, stage, stage_cap, scratch, out,
                                         base_b, mode, dbg_bitmap, dbg_prefix,
                                         static_cast<uint64_t>(b) * slice_words);
-  if (mode != kEmit) return;
+  if (mode == kEmit && tid == 0) {
+    info[3 * b] = base_b;
+    info[3 * b + 1] = pop;
+    info[3 * b + 2] = cnt_b;
+  }
+}
 
-  if (tid == 0) {
-    binfo[2 * b] = base_b;
-    binfo[2 * b + 1] = pop;
+// Status of a two-kernel sort, after k_slice: flags, number of keys written,
+// and the compaction a duplicate calls for.  One workgroup.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_finish(uint64_t n, uint32_t nb, const uint64_t* __restrict__ info,
+                                                  Status* status, uint32_t* out) {
+  __shared__ uint64_t scratch64[BLOCK / kWave];
+  uint64_t pop = 0, dup = 0;
+  for (uint32_t b = threadIdx.x; b < nb; b += BLOCK) {
+    const uint64_t p = info[3 * b + 1];
+    pop += p;
+    dup += (p != info[3 * b + 2]) ? 1u : 0u;
+  }
+  pop = block_sum_u64<BLOCK>(pop, scratch64);
+  dup = block_sum_u64<BLOCK>(dup, scratch64);
+  const uint64_t valid = uniform(info[3 * (nb - 1)] + info[3 * (nb - 1) + 2]);  // keys below 2^range_bits
+  if (threadIdx.x == 0) {
     uint32_t f = 0;
-    if (pop != cnt_b) f |= BITSORT_STATUS_DUPLICATE;
-    if (b == nb - 1u && base_b + cnt_b != n) f |= BITSORT_STATUS_OUT_OF_RANGE;
-    if (f) atomicOr(&status->flags, f);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&status->count),
-              static_cast<unsigned long long>(pop));
+    if (valid != n) f |= BITSORT_STATUS_OUT_OF_RANGE;
+    if (dup != 0) f |= BITSORT_STATUS_DUPLICATE;
+    status->flags = f;
+    status->done = 0;
+    status->count = pop;
   }
-  // The last slice to finish compacts the output if a duplicate left gaps.
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) scratch[0] = (atomicAdd(&status->done, 1u) == nb - 1u) ? 1u : 0u;
-  __syncthreads();
-  if (uniform(scratch[0])) {
-    __threadfence();
-    if (uniform(atomic_load_flags(&status->flags)) & BITSORT_STATUS_DUPLICATE) compact_slices<BLOCK>(out, binfo, nb);
-  }
+  if (dup != 0) compact_slices<BLOCK>(out, info, nb);
 }
 
 // ---------------------------------------------------------------------------
@@ -645,7 +725,7 @@ void make_plan(uint64_t n, uint32_t rb, Plan* p) {
     p->tile_keys = 1u << tl;
     p->nt = static_cast<uint32_t>((n + p->tile_keys - 1) >> tl);
     p->off_binfo = kHeaderBytes;
-    p->off_table = align256(p->off_binfo + 16ull * p->nb);
+    p->off_table = align256(p->off_binfo + 24ull * p->nb);
     p->off_staging = align256(p->off_table + 4ull * p->nt * (p->nb + 1));
     p->bytes = align256(p->off_staging + 4ull * p->nt * p->tile_keys);
   }
@@ -694,6 +774,42 @@ int launch_status() {
   return e == hipSuccess ? BITSORT_OK : BITSORT_ERR_HIP;
 }
 
+// Kernel timing (bitsort_profile_*): events bracketing each launch.
+enum KernelId : int { kKPartition = 0, kKSlice, kKFinish, kKDirect, kKBatchPlan, kKBatchRun, kKCount };
+const char* const kKernelNames[kKCount] = {"k_partition", "k_slice", "k_finish", "k_direct", "k_batch_plan",
+                                           "k_batch_run"};
+struct PendingTiming {
+  int kernel;
+  hipEvent_t start, stop;
+};
+std::atomic<bool> g_prof_on{false};
+std::mutex g_prof_mu;
+std::vector<PendingTiming> g_prof_pending;
+uint64_t g_prof_launches[kKCount] = {};
+double g_prof_ms[kKCount] = {};
+
+// Records the start event of a timed launch (no-op while profiling is off).
+struct LaunchTimer {
+  int kernel;
+  hipStream_t stream;
+  hipEvent_t start = nullptr;
+  LaunchTimer(int k, hipStream_t s) : kernel(k), stream(s) {
+    if (!g_prof_on.load(std::memory_order_relaxed)) return;
+    if (hipEventCreate(&start) != hipSuccess || hipEventRecord(start, stream) != hipSuccess) start = nullptr;
+  }
+  ~LaunchTimer() {
+    if (start == nullptr) return;
+    hipEvent_t stop = nullptr;
+    if (hipEventCreate(&stop) != hipSuccess || hipEventRecord(stop, stream) != hipSuccess) {
+      (void)hipEventDestroy(start);
+      if (stop) (void)hipEventDestroy(stop);
+      return;
+    }
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    g_prof_pending.push_back({kernel, start, stop});
+  }
+};
+
 // Enqueue the plain path.  mode != kEmit writes the debug dumps instead.
 int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, void* ws,
               hipStream_t stream, int mode, uint32_t* dbg_bitmap, uint64_t* dbg_prefix) {
@@ -703,34 +819,46 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
   Status* status = reinterpret_cast<Status*>(base);
   const uint64_t range = 1ull << p.rb;
   if (p.direct) {
+    LaunchTimer timer(kKDirect, stream);
     hipLaunchKernelGGL(k_direct<kDirectBlock>, dim3(1), dim3(kDirectBlock), p.slice_lds, stream, keys, n,
                        range, p.sb, p.stage_cap, out, status, mode, dbg_bitmap, dbg_prefix);
     return launch_status();
   }
   uint32_t* table = reinterpret_cast<uint32_t*>(base + p.off_table);
   uint32_t* staging = reinterpret_cast<uint32_t*>(base + p.off_staging);
-  uint64_t* binfo = reinterpret_cast<uint64_t*>(base + p.off_binfo);
+  uint64_t* info = reinterpret_cast<uint64_t*>(base + p.off_binfo);
   const int vec_ok = (reinterpret_cast<uintptr_t>(keys) % 16u) == 0 ? 1 : 0;
   const size_t part_lds = 4ull * (32 + round_up4(p.nb) + p.tile_keys);
-  switch (p.tile_log2) {
-    case 12:
-      hipLaunchKernelGGL((k_partition<256, 16>), dim3(p.nt), dim3(256), part_lds, stream, keys, n, range,
-                         p.sb, p.nb, staging, table, status, vec_ok);
-      break;
-    case 13:
-      hipLaunchKernelGGL((k_partition<512, 16>), dim3(p.nt), dim3(512), part_lds, stream, keys, n, range,
-                         p.sb, p.nb, staging, table, status, vec_ok);
-      break;
-    default:
-      hipLaunchKernelGGL((k_partition<1024, 16>), dim3(p.nt), dim3(1024), part_lds, stream, keys, n, range,
-                         p.sb, p.nb, staging, table, status, vec_ok);
-      break;
+  {
+    LaunchTimer timer(kKPartition, stream);
+    switch (p.tile_log2) {
+      case 12:
+        hipLaunchKernelGGL((k_partition<256, 16>), dim3(p.nt), dim3(256), part_lds, stream, keys, n, range,
+                           p.sb, p.nb, staging, table, vec_ok);
+        break;
+      case 13:
+        hipLaunchKernelGGL((k_partition<512, 16>), dim3(p.nt), dim3(512), part_lds, stream, keys, n, range,
+                           p.sb, p.nb, staging, table, vec_ok);
+        break;
+      default:
+        hipLaunchKernelGGL((k_partition<1024, 16>), dim3(p.nt), dim3(1024), part_lds, stream, keys, n, range,
+                           p.sb, p.nb, staging, table, vec_ok);
+        break;
+    }
+    rc = launch_status();
   }
-  rc = launch_status();
   if (rc != BITSORT_OK) return rc;
-  hipLaunchKernelGGL((k_slice<kSliceBlock, kSliceUnroll>), dim3(p.nb), dim3(kSliceBlock), p.slice_lds, stream,
-                     staging, table, p.nt, p.tile_keys, n, p.sb, p.nb, p.stage_cap, out, status, binfo, mode,
-                     dbg_bitmap, dbg_prefix);
+  {
+    LaunchTimer timer(kKSlice, stream);
+    const uint32_t grid = 8u * ((p.nb + 7u) / 8u);
+    hipLaunchKernelGGL((k_slice<kSliceBlock, kSliceUnroll>), dim3(grid), dim3(kSliceBlock), p.slice_lds, stream,
+                       staging, table, p.nt, p.tile_keys, p.sb, p.nb, p.stage_cap, out, info, mode, dbg_bitmap,
+                       dbg_prefix);
+    rc = launch_status();
+  }
+  if (rc != BITSORT_OK || mode != kEmit) return rc;
+  LaunchTimer timer(kKFinish, stream);
+  hipLaunchKernelGGL((k_finish<kSliceBlock>), dim3(1), dim3(kSliceBlock), 0, stream, n, p.nb, info, status, out);
   return launch_status();
 }
 
@@ -944,9 +1072,12 @@ int bitsort_batch_u32(const uint32_t* keys, const uint64_t* offsets, uint32_t nu
   uint32_t* counter = reinterpret_cast<uint32_t*>(base);
   SegStatus* st = reinterpret_cast<SegStatus*>(base + off_status);
   uint2* items = reinterpret_cast<uint2*>(base + off_items);
-  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, s, offsets, range_bits, num_segments, max_keys, sbb,
-                     items, counter, st);
-  rc = launch_status();
+  {
+    LaunchTimer timer(kKBatchPlan, s);
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, s, offsets, range_bits, num_segments, max_keys, sbb,
+                       items, counter, st);
+    rc = launch_status();
+  }
   if (rc != BITSORT_OK) return rc;
   const uint32_t stage_cap = stage_cap_for(sbb);
   const size_t lds = slice_lds_bytes(sbb, stage_cap);
@@ -954,6 +1085,7 @@ int bitsort_batch_u32(const uint32_t* keys, const uint64_t* offsets, uint32_t nu
   int dev = 0;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const uint64_t grid = std::min<uint64_t>(static_cast<uint64_t>(cus), max_items);
+  LaunchTimer timer(kKBatchRun, s);
   hipLaunchKernelGGL(k_batch_run<kBatchBlock>, dim3(static_cast<uint32_t>(grid)), dim3(kBatchBlock), lds, s, keys,
                      offsets, range_bits, sbb, stage_cap, items, counter, out, st);
   return launch_status();
@@ -976,6 +1108,55 @@ int bitsort_batch_status(bitsort_stream_t stream, bitsort_status_t* status, uint
                 hipMemcpyDeviceToHost) != hipSuccess)
     return BITSORT_ERR_HIP;
   return BITSORT_OK;
+}
+
+int bitsort_profile_enable(int on) {
+  g_prof_on.store(on != 0);
+  return BITSORT_OK;
+}
+
+int bitsort_profile_reset(void) {
+  std::lock_guard<std::mutex> lock(g_prof_mu);
+  for (auto& t : g_prof_pending) {
+    (void)hipEventSynchronize(t.stop);
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  g_prof_pending.clear();
+  for (int k = 0; k < kKCount; ++k) {
+    g_prof_launches[k] = 0;
+    g_prof_ms[k] = 0.0;
+  }
+  return BITSORT_OK;
+}
+
+int bitsort_profile_read(bitsort_profile_entry_t* entries, int max_entries, int* n_entries) {
+  if (n_entries == nullptr || (max_entries > 0 && entries == nullptr)) return BITSORT_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_prof_mu);
+  int rc = BITSORT_OK;
+  for (auto& t : g_prof_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.stop) != hipSuccess || hipEventElapsedTime(&ms, t.start, t.stop) != hipSuccess)
+      rc = BITSORT_ERR_HIP;
+    g_prof_launches[t.kernel] += 1;
+    g_prof_ms[t.kernel] += ms;
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  g_prof_pending.clear();
+  int n = 0;
+  for (int k = 0; k < kKCount; ++k) {
+    if (g_prof_launches[k] == 0) continue;
+    if (n < max_entries) {
+      std::memset(entries[n].kernel, 0, sizeof(entries[n].kernel));
+      std::strncpy(entries[n].kernel, kKernelNames[k], sizeof(entries[n].kernel) - 1);
+      entries[n].launches = g_prof_launches[k];
+      entries[n].total_ms = g_prof_ms[k];
+    }
+    ++n;
+  }
+  *n_entries = n;
+  return rc;
 }
 
 int bitsort_set_tuning(uint32_t slice_bits, uint32_t tile_log2) {
