@@ -163,15 +163,22 @@ int bitsort_debug_prefix_u32(const uint32_t *keys, uint64_t n, uint32_t range_bi
                              uint64_t *prefix, bitsort_stream_t stream);
 
 /*
- * Tuning knobs for the plain path (0 = library default).  slice_bits: bits
- * of key range per LDS slice (10..20); tile_log2: keys per partition tile as
- * a power of two (12..14).  Affects calls made afterwards in this process.
+ * Tuning knobs for the plain path (0 = library default).
+ *   slice_bits  bits of key range per LDS slice (10..20);
+ *   tile_log2   keys per partition tile as a power of two (12..15);
+ *   emit_path   1: emit each slice from LDS (k_slice); 2: write the bit-vector
+ *               to HBM and emit from it at full occupancy (k_slice + k_emit,
+ *               needs slice_bits >= 15); 0: choose by size (the HBM bit-vector
+ *               when R/8 <= 2n).
+ * Affects calls made afterwards in this process.
  */
-int bitsort_set_tuning(uint32_t slice_bits, uint32_t tile_log2);
+int bitsort_set_tuning(uint32_t slice_bits, uint32_t tile_log2, uint32_t emit_path);
 
-/* The slice_bits and tile_log2 the plain path would use for (n, range_bits). */
+/* The slice_bits, tile_log2 (0 for the single-workgroup path), number of
+ * slices and emit path (0 single workgroup, 1 LDS, 2 HBM bit-vector) that the
+ * plain path would use for (n, range_bits). */
 int bitsort_plan_info(uint64_t n, uint32_t range_bits, uint32_t *slice_bits, uint32_t *tile_log2,
-                      uint32_t *buckets);
+                      uint32_t *buckets, uint32_t *emit_path);
 
 /*
  * Kernel timing for benchmarks.  While enabled, every kernel the library
@@ -182,7 +189,7 @@ int bitsort_plan_info(uint64_t n, uint32_t range_bits, uint32_t *slice_bits, uin
  * Enabling costs two event records per kernel launch.
  */
 typedef struct bitsort_profile_entry {
-    char kernel[32];      /* k_partition, k_slice, k_direct, k_batch_plan, k_batch_run */
+    char kernel[32];      /* k_partition, k_slice, k_emit, k_finish, k_direct, k_batch_plan, k_batch_run */
     uint64_t launches;
     double total_ms;
 } bitsort_profile_entry_t;

@@ -148,11 +148,14 @@ def debug_prefix(keys, range_bits: int, stream=None):
     return pre
 
 
-def set_tuning(slice_bits: int = 0, tile_log2: int = 0) -> None:
-    _lib.check(_lib.bitsort_set_tuning(slice_bits, tile_log2), "bitsort_set_tuning")
+def set_tuning(slice_bits: int = 0, tile_log2: int = 0, emit_path: int = 0) -> None:
+    _lib.check(_lib.bitsort_set_tuning(slice_bits, tile_log2, emit_path), "bitsort_set_tuning")
+
+
+EMIT_PATHS = {0: "single-workgroup", 1: "lds", 2: "hbm-bitvector"}
 
 
 def plan_info(n: int, range_bits: int):
-    rc, sb, tl, nb = _lib.bitsort_plan_info(n, range_bits)
+    rc, sb, tl, nb, ep = _lib.bitsort_plan_info(n, range_bits)
     _lib.check(rc, "bitsort_plan_info")
-    return {"slice_bits": sb, "tile_log2": tl, "buckets": nb}
+    return {"slice_bits": sb, "tile_log2": tl, "buckets": nb, "emit_path": EMIT_PATHS[ep]}

@@ -55,8 +55,9 @@ _SIGS = {
     "bitsort_generate_u32": (_c.c_int, [_vp, _u64, _u64, _u32, _u64, _vp]),
     "bitsort_debug_bitmap_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
     "bitsort_debug_prefix_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
-    "bitsort_set_tuning": (_c.c_int, [_u32, _u32]),
-    "bitsort_plan_info": (_c.c_int, [_u64, _u32, _c.POINTER(_u32), _c.POINTER(_u32), _c.POINTER(_u32)]),
+    "bitsort_set_tuning": (_c.c_int, [_u32, _u32, _u32]),
+    "bitsort_plan_info": (_c.c_int, [_u64, _u32, _c.POINTER(_u32), _c.POINTER(_u32), _c.POINTER(_u32),
+                                     _c.POINTER(_u32)]),
     "bitsort_profile_enable": (_c.c_int, [_c.c_int]),
     "bitsort_profile_reset": (_c.c_int, []),
     "bitsort_profile_read": (_c.c_int, [_c.POINTER(ProfileEntry), _c.c_int, _c.POINTER(_c.c_int)]),
@@ -73,6 +74,14 @@ def lib():
             raise FileNotFoundError(
                 f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
                 "(hipcc, --offload-arch=gfx950)")
+        # torch ships its own libamdhip64 (same soname).  Loading it first makes
+        # this library bind to that runtime, so device pointers and streams
+        # from torch are valid here; loading this library first would map a
+        # second HIP runtime into the process.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         handle = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(handle, name)
@@ -151,14 +160,15 @@ def bitsort_debug_prefix_u32(keys: int, n: int, range_bits: int, prefix: int, st
     return lib().bitsort_debug_prefix_u32(keys, n, range_bits, prefix, stream)
 
 
-def bitsort_set_tuning(slice_bits: int, tile_log2: int) -> int:
-    return lib().bitsort_set_tuning(slice_bits, tile_log2)
+def bitsort_set_tuning(slice_bits: int, tile_log2: int, emit_path: int = 0) -> int:
+    return lib().bitsort_set_tuning(slice_bits, tile_log2, emit_path)
 
 
 def bitsort_plan_info(n: int, range_bits: int):
-    sb, tl, nb = _u32(), _u32(), _u32()
-    rc = lib().bitsort_plan_info(n, range_bits, ctypes.byref(sb), ctypes.byref(tl), ctypes.byref(nb))
-    return rc, sb.value, tl.value, nb.value
+    sb, tl, nb, ep = _u32(), _u32(), _u32(), _u32()
+    rc = lib().bitsort_plan_info(n, range_bits, ctypes.byref(sb), ctypes.byref(tl), ctypes.byref(nb),
+                                 ctypes.byref(ep))
+    return rc, sb.value, tl.value, nb.value, ep.value
 
 
 def bitsort_profile_enable(on: bool) -> int:

@@ -67,8 +67,11 @@ constexpr uint32_t kHeaderBytes = 256;        // status + scratch header in LDS 
 constexpr uint32_t kStageMax = 8192;
 constexpr uint32_t kBatchBlock = 1024;
 constexpr uint32_t kBatchSliceBits = 20;
+constexpr uint32_t kChunkWords = 1024;        // words per k_emit workgroup
+constexpr uint32_t kEmitBlock = 256;
+constexpr uint32_t kEmitWindow = 1024;        // LDS window per wave in k_emit (words)
 
-enum Mode : int { kEmit = 0, kDumpBitmap = 1, kDumpPrefix = 2 };
+enum Mode : int { kEmit = 0, kDumpBitmap = 1, kDumpPrefix = 2, kToBitVector = 3 };
 
 __host__ __device__ constexpr uint32_t round_up4(uint32_t x) { return (x + 3u) & ~3u; }
 
@@ -353,7 +356,8 @@ __global__ __launch_bounds__(BLOCK) void k_slice(const uint32_t* __restrict__ st
                                                  uint32_t tile_keys, uint32_t sb, uint32_t nb,
                                                  uint32_t stage_cap, uint32_t* __restrict__ out,
                                                  uint64_t* __restrict__ info, int mode,
-                                                 uint32_t* dbg_bitmap, uint64_t* dbg_prefix) {
+                                                 uint32_t* dbg_bitmap, uint64_t* dbg_prefix,
+                                                 uint32_t* __restrict__ bitvec, uint64_t* __restrict__ chunk_base) {
   constexpr uint32_t kWaves = BLOCK / kWave;
   extern __shared__ __align__(16) uint32_t lds[];
   uint64_t* scratch64 = reinterpret_cast<uint64_t*>(lds);
@@ -405,6 +409,40 @@ __global__ __launch_bounds__(BLOCK) void k_slice(const uint32_t* __restrict__ st
   const uint64_t base_b = block_sum_u64<BLOCK>(base_acc, scratch64);  // also orders the marks before the scan
   const uint64_t cnt_b = block_sum_u64<BLOCK>(cnt_acc, scratch64);
 
+  if (mode == kToBitVector) {
+    // Scan step only: the slice goes to the bit-vector in HBM, and every
+    // kChunkWords-word chunk gets its exclusive prefix of set bits over the
+    // whole bit-vector (the slice's base plus the chunks before it).
+    const uint32_t nchunk = slice_words / kChunkWords;
+    for (uint32_t c = wave; c < nchunk; c += kWaves) {
+      uint32_t cnt = 0;
+      for (uint32_t w = c * kChunkWords + lane; w < (c + 1) * kChunkWords; w += kWave)
+        cnt += static_cast<uint32_t>(__popc(slice[w]));
+      cnt = wave_sum_u32(cnt);
+      if (lane == 0) stage[c] = cnt;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      uint64_t run = base_b;  // nchunk <= 32: one wave scans the chunk counts
+      for (uint32_t c0 = 0; c0 < nchunk; c0 += kWave) {
+        const uint32_t c = c0 + lane;
+        const uint32_t v = c < nchunk ? stage[c] : 0u;
+        const uint32_t inc = wave_incl_scan(v);
+        if (c < nchunk) chunk_base[static_cast<uint64_t>(b) * nchunk + c] = run + inc - v;
+        run += uniform(static_cast<uint32_t>(__shfl(inc, kWave - 1, kWave)));
+      }
+      if (lane == 0) {
+        info[3 * b] = base_b;
+        info[3 * b + 1] = run - base_b;
+        info[3 * b + 2] = cnt_b;
+      }
+    }
+    const uint4* src4 = reinterpret_cast<const uint4*>(slice);
+    uint4* dst4 = reinterpret_cast<uint4*>(bitvec + static_cast<uint64_t>(b) * slice_words);
+    for (uint32_t i = tid; i < slice_words / 4u; i += BLOCK) dst4[i] = src4[i];
+    return;
+  }
+
   const uint32_t key_base = b << sb;
   const uint64_t pop = scan_emit<BLOCK>(slice, slice_words, key_base, stage, stage_cap, scratch, out,
                                         base_b, mode, dbg_bitmap, dbg_prefix,
@@ -413,6 +451,92 @@ __global__ __launch_bounds__(BLOCK) void k_slice(const uint32_t* __restrict__ st
     info[3 * b] = base_b;
     info[3 * b + 1] = pop;
     info[3 * b + 2] = cnt_b;
+  }
+}
+
+// Emit from the bit-vector in HBM (after k_slice in kToBitVector mode): one
+// workgroup per kChunkWords-word chunk, whose exclusive prefix of set bits
+// k_slice already wrote.  Each wave owns a quarter of the chunk, loads its
+// words into registers (4 per lane), counts them, and after one barrier emits
+// 64 words at a time exactly like scan_emit: straight stores for sparse and
+// full-word groups, otherwise an LDS window of kEmitWindow keys per wave.
+// Small LDS and small workgroups keep 32 waves on every CU.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_emit(const uint32_t* __restrict__ bitvec,
+                                                const uint64_t* __restrict__ chunk_base,
+                                                uint32_t* __restrict__ out, int mode, uint64_t* dbg_prefix) {
+  constexpr uint32_t kWaves = BLOCK / kWave;
+  constexpr uint32_t kPer = kChunkWords / kWaves;  // words per wave
+  constexpr uint32_t kGroups = kPer / kWave;       // 64-word groups per wave
+  __shared__ uint32_t scratch[kWaves];
+  __shared__ __align__(16) uint32_t stage[kWaves * (kEmitWindow + 4)];
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t wave = threadIdx.x / kWave;
+  const uint64_t w_lo = static_cast<uint64_t>(blockIdx.x) * kChunkWords + wave * kPer;
+  uint32_t x[kGroups];
+  uint32_t cnt = 0;
+#pragma unroll
+  for (uint32_t g = 0; g < kGroups; ++g) {
+    x[g] = bitvec[w_lo + g * kWave + lane];
+    cnt += static_cast<uint32_t>(__popc(x[g]));
+  }
+  cnt = wave_sum_u32(cnt);
+  if (lane == 0) scratch[wave] = cnt;
+  __syncthreads();
+  uint64_t D = chunk_base[blockIdx.x];
+#pragma unroll
+  for (uint32_t i = 0; i < kWaves; ++i) D += (i < wave) ? scratch[i] : 0u;
+  D = uniform(D);
+  uint32_t* ws = stage + wave * (kEmitWindow + 4);
+#pragma unroll
+  for (uint32_t g = 0; g < kGroups; ++g) {
+    const uint64_t gw = w_lo + g * kWave + lane;  // global word index: its keys are 32*gw + bit
+    const uint32_t xg = x[g];
+    const uint32_t c = static_cast<uint32_t>(__popc(xg));
+    if (mode == kEmit) {
+      const uint64_t nz = __ballot(c != 0u);
+      if (nz == 0) continue;
+      if (__ballot(c > 1u) == 0) {
+        if (c != 0u) out[D + count_below(nz)] = static_cast<uint32_t>(gw << 5) + static_cast<uint32_t>(__builtin_ctz(xg));
+        D += static_cast<uint32_t>(__popcll(nz));
+        continue;
+      }
+      if (__ballot(xg != 0xFFFFFFFFu) == 0) {
+        const uint32_t kb0 = static_cast<uint32_t>((w_lo + g * kWave) << 5);
+#pragma unroll 8
+        for (uint32_t j = 0; j < 32; ++j) out[D + j * kWave + lane] = kb0 + j * kWave + lane;
+        D += 32u * kWave;
+        continue;
+      }
+    }
+    uint32_t tot;
+    const uint32_t p = wave_prefix_small(c, &tot);
+    tot = uniform(tot);
+    if (mode == kDumpPrefix) {
+      dbg_prefix[gw] = D + p;
+    } else if (mode == kEmit) {
+      for (uint32_t lo = 0; lo < tot; lo += kEmitWindow) {
+        uint32_t* dst = out + D + lo;
+        const uint32_t shift = static_cast<uint32_t>((reinterpret_cast<uintptr_t>(dst) >> 2) & 3u);
+        if (c != 0u && p < lo + kEmitWindow && p + c > lo) {
+          uint32_t y = xg, pos = p;
+          while (pos < lo) {
+            y &= y - 1u;
+            ++pos;
+          }
+          const uint32_t kb = static_cast<uint32_t>(gw << 5);
+          while (y != 0u && pos < lo + kEmitWindow) {
+            ws[shift + pos - lo] = kb + static_cast<uint32_t>(__builtin_ctz(y));
+            y &= y - 1u;
+            ++pos;
+          }
+        }
+        wave_sync();
+        wave_copy_out(ws, shift, dst, min(kEmitWindow, tot - lo));
+        wave_sync();
+      }
+    }
+    D += tot;
   }
 }
 
@@ -678,13 +802,16 @@ __global__ __launch_bounds__(BLOCK) void k_batch_run(const uint32_t* __restrict_
 struct Plan {
   uint32_t rb = 0, sb = 0, nb = 1, tile_log2 = 0, tile_keys = 0, nt = 0;
   bool direct = true;
-  size_t off_binfo = 0, off_table = 0, off_staging = 0, bytes = 0;
+  bool via_bitvec = false;  // k_slice writes the bit-vector to HBM, k_emit writes the keys
+  uint64_t n_chunks = 0;
+  size_t off_binfo = 0, off_table = 0, off_staging = 0, off_bitvec = 0, off_chunk = 0, bytes = 0;
   uint32_t stage_cap = 0;
   size_t slice_lds = 0;
 };
 
 std::atomic<uint32_t> g_tune_sb{0};
 std::atomic<uint32_t> g_tune_tile{0};
+std::atomic<uint32_t> g_tune_path{0};  // 0 auto, 1 emit from LDS, 2 through the HBM bit-vector
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
@@ -720,7 +847,7 @@ void make_plan(uint64_t n, uint32_t rb, Plan* p) {
     p->nb = 1u << (rb - sb);
     uint32_t tl = g_tune_tile.load();
     if (tl == 0) tl = n >= (1ull << 22) ? 14 : 12;
-    tl = std::min<uint32_t>(std::max<uint32_t>(tl, 12), 14);
+    tl = std::min<uint32_t>(std::max<uint32_t>(tl, 12), 15);
     p->tile_log2 = tl;
     p->tile_keys = 1u << tl;
     p->nt = static_cast<uint32_t>((n + p->tile_keys - 1) >> tl);
@@ -728,6 +855,18 @@ void make_plan(uint64_t n, uint32_t rb, Plan* p) {
     p->off_table = align256(p->off_binfo + 24ull * p->nb);
     p->off_staging = align256(p->off_table + 4ull * p->nt * (p->nb + 1));
     p->bytes = align256(p->off_staging + 4ull * p->nt * p->tile_keys);
+    // Emit through an HBM bit-vector when it is small next to the keys
+    // (R/8 <= 2n): the bit-vector round trip costs 2R/8 bytes, and in return
+    // the emission runs at full occupancy instead of beside a 2^sb-bit slice.
+    const uint32_t path = g_tune_path.load();
+    const uint64_t bv_bytes = (1ull << rb) / 8u;
+    if ((1u << (sb - 5)) >= kChunkWords && (path == 2 || (path == 0 && bv_bytes <= 2 * n))) {
+      p->via_bitvec = true;
+      p->n_chunks = (1ull << (rb - 5)) / kChunkWords;
+      p->off_bitvec = p->bytes;
+      p->off_chunk = align256(p->off_bitvec + bv_bytes);
+      p->bytes = align256(p->off_chunk + 8ull * p->n_chunks);
+    }
   }
   p->stage_cap = stage_cap_for(p->sb);
   p->slice_lds = slice_lds_bytes(p->sb, p->stage_cap);
@@ -762,6 +901,7 @@ int init_kernels() {
     set_lds_attr(k_partition<256, 16>, kLdsBytes);
     set_lds_attr(k_partition<512, 16>, kLdsBytes);
     set_lds_attr(k_partition<1024, 16>, kLdsBytes);
+    set_lds_attr(k_partition<1024, 32>, kLdsBytes);
     set_lds_attr(k_slice<kSliceBlock, kSliceUnroll>, kLdsBytes);
     set_lds_attr(k_direct<kDirectBlock>, kLdsBytes);
     set_lds_attr(k_batch_run<kBatchBlock>, kLdsBytes);
@@ -775,9 +915,9 @@ int launch_status() {
 }
 
 // Kernel timing (bitsort_profile_*): events bracketing each launch.
-enum KernelId : int { kKPartition = 0, kKSlice, kKFinish, kKDirect, kKBatchPlan, kKBatchRun, kKCount };
-const char* const kKernelNames[kKCount] = {"k_partition", "k_slice", "k_finish", "k_direct", "k_batch_plan",
-                                           "k_batch_run"};
+enum KernelId : int { kKPartition = 0, kKSlice, kKEmit, kKFinish, kKDirect, kKBatchPlan, kKBatchRun, kKCount };
+const char* const kKernelNames[kKCount] = {"k_partition", "k_slice", "k_emit", "k_finish", "k_direct",
+                                           "k_batch_plan", "k_batch_run"};
 struct PendingTiming {
   int kernel;
   hipEvent_t start, stop;
@@ -840,23 +980,38 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
         hipLaunchKernelGGL((k_partition<512, 16>), dim3(p.nt), dim3(512), part_lds, stream, keys, n, range,
                            p.sb, p.nb, staging, table, vec_ok);
         break;
-      default:
+      case 14:
         hipLaunchKernelGGL((k_partition<1024, 16>), dim3(p.nt), dim3(1024), part_lds, stream, keys, n, range,
+                           p.sb, p.nb, staging, table, vec_ok);
+        break;
+      default:
+        hipLaunchKernelGGL((k_partition<1024, 32>), dim3(p.nt), dim3(1024), part_lds, stream, keys, n, range,
                            p.sb, p.nb, staging, table, vec_ok);
         break;
     }
     rc = launch_status();
   }
   if (rc != BITSORT_OK) return rc;
+  uint32_t* bitvec = reinterpret_cast<uint32_t*>(base + p.off_bitvec);
+  uint64_t* chunk_base = reinterpret_cast<uint64_t*>(base + p.off_chunk);
+  if (p.via_bitvec && mode == kDumpBitmap) bitvec = dbg_bitmap;  // the mark step's bit-vector is the dump
   {
     LaunchTimer timer(kKSlice, stream);
     const uint32_t grid = 8u * ((p.nb + 7u) / 8u);
     hipLaunchKernelGGL((k_slice<kSliceBlock, kSliceUnroll>), dim3(grid), dim3(kSliceBlock), p.slice_lds, stream,
-                       staging, table, p.nt, p.tile_keys, p.sb, p.nb, p.stage_cap, out, info, mode, dbg_bitmap,
-                       dbg_prefix);
+                       staging, table, p.nt, p.tile_keys, p.sb, p.nb, p.stage_cap, out, info,
+                       p.via_bitvec ? static_cast<int>(kToBitVector) : mode, dbg_bitmap, dbg_prefix, bitvec,
+                       chunk_base);
     rc = launch_status();
   }
-  if (rc != BITSORT_OK || mode != kEmit) return rc;
+  if (rc != BITSORT_OK || mode == kDumpBitmap || (mode == kDumpPrefix && !p.via_bitvec)) return rc;
+  if (p.via_bitvec) {
+    LaunchTimer timer(kKEmit, stream);
+    hipLaunchKernelGGL((k_emit<kEmitBlock>), dim3(static_cast<uint32_t>(p.n_chunks)), dim3(kEmitBlock), 0, stream,
+                       bitvec, chunk_base, out, mode, dbg_prefix);
+    rc = launch_status();
+    if (rc != BITSORT_OK || mode != kEmit) return rc;
+  }
   LaunchTimer timer(kKFinish, stream);
   hipLaunchKernelGGL((k_finish<kSliceBlock>), dim3(1), dim3(kSliceBlock), 0, stream, n, p.nb, info, status, out);
   return launch_status();
@@ -1159,23 +1314,27 @@ int bitsort_profile_read(bitsort_profile_entry_t* entries, int max_entries, int*
   return rc;
 }
 
-int bitsort_set_tuning(uint32_t slice_bits, uint32_t tile_log2) {
+int bitsort_set_tuning(uint32_t slice_bits, uint32_t tile_log2, uint32_t emit_path) {
   if (slice_bits != 0 && (slice_bits < kMinSliceBits || slice_bits > kMaxSliceBits)) return BITSORT_ERR_INVALID_ARG;
-  if (tile_log2 != 0 && (tile_log2 < 12 || tile_log2 > 14)) return BITSORT_ERR_INVALID_ARG;
+  if (tile_log2 != 0 && (tile_log2 < 12 || tile_log2 > 15)) return BITSORT_ERR_INVALID_ARG;
+  if (emit_path > 2) return BITSORT_ERR_INVALID_ARG;
   g_tune_sb.store(slice_bits);
   g_tune_tile.store(tile_log2);
+  g_tune_path.store(emit_path);
   return BITSORT_OK;
 }
 
 int bitsort_plan_info(uint64_t n, uint32_t range_bits, uint32_t* slice_bits, uint32_t* tile_log2,
-                      uint32_t* buckets) {
-  if (range_bits > 32 || slice_bits == nullptr || tile_log2 == nullptr || buckets == nullptr)
+                      uint32_t* buckets, uint32_t* emit_path) {
+  if (range_bits > 32 || slice_bits == nullptr || tile_log2 == nullptr || buckets == nullptr ||
+      emit_path == nullptr)
     return BITSORT_ERR_INVALID_ARG;
   Plan p;
   make_plan(n, range_bits, &p);
   *slice_bits = p.sb;
   *tile_log2 = p.direct ? 0 : p.tile_log2;
   *buckets = p.nb;
+  *emit_path = p.direct ? 0u : (p.via_bitvec ? 2u : 1u);
   return BITSORT_OK;
 }
 

@@ -107,23 +107,72 @@ def test_parity_sparse_full_range(o):
     np.testing.assert_array_equal(got, want)
 
 
-@pytest.mark.parametrize("n,rb", [(3000, 12), (1 << 20, 20), (1_000_000, 24), (40_000, 27)])
-def test_mark_step_matches_oracle_bitmap(o, n, rb):
+# (n, range_bits, emit path): 0 = library choice, 1 = from LDS, 2 = through the HBM bit-vector
+STEP_CASES = [(3000, 12, 0), (1 << 20, 20, 0), (1_000_000, 24, 1), (1_000_000, 24, 2), (40_000, 27, 0),
+              ((1 << 22) + 3, 24, 0), (1 << 22, 26, 2)]
+
+
+@pytest.mark.parametrize("n,rb,path", STEP_CASES)
+def test_mark_step_matches_oracle_bitmap(o, n, rb, path):
     import paper_1312_0138_amd as bs
     keys = inputs.distinct_uniform(n, rb, 77)
     want, _ = o.bitmap_build(keys, rb)
-    got = to_np(bs.debug_bitmap(to_dev(keys), rb))
+    bs.set_tuning(0, 0, path)
+    try:
+        got = to_np(bs.debug_bitmap(to_dev(keys), rb))
+    finally:
+        bs.set_tuning(0, 0, 0)
     np.testing.assert_array_equal(got, want)
 
 
-@pytest.mark.parametrize("n,rb", [(3000, 12), (1 << 20, 20), (1_000_000, 24)])
-def test_scan_step_matches_oracle_prefix(o, n, rb):
+@pytest.mark.parametrize("n,rb,path", STEP_CASES)
+def test_scan_step_matches_oracle_prefix(o, n, rb, path):
     import paper_1312_0138_amd as bs
     keys = inputs.distinct_uniform(n, rb, 78)
     words, _ = o.bitmap_build(keys, rb)
     want = o.bitmap_scan(words)[:-1]
-    got = bs.debug_prefix(to_dev(keys), rb).cpu().numpy().astype(np.uint64)
+    bs.set_tuning(0, 0, path)
+    try:
+        got = bs.debug_prefix(to_dev(keys), rb).cpu().numpy().astype(np.uint64)
+    finally:
+        bs.set_tuning(0, 0, 0)
     np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("n,rb", [(1 << 20, 24), (3_000_001, 26), (1 << 24, 28)])
+def test_both_emit_paths(o, n, rb, path):
+    import paper_1312_0138_amd as bs
+    keys = inputs.distinct_uniform(n, rb, 79)
+    want, _, _ = o.bitmap_sort(keys, rb)
+    bs.set_tuning(0, 0, path)
+    try:
+        assert bs.plan_info(n, rb)["emit_path"] == {1: "lds", 2: "hbm-bitvector"}[path]
+        got, st = _gpu_sort(keys, rb)
+    finally:
+        bs.set_tuning(0, 0, 0)
+    assert st.flags == 0 and st.count == n
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_duplicates_and_range_on_both_paths(o, path):
+    import paper_1312_0138_amd as bs
+    base = inputs.distinct_uniform(1 << 21, 25, 81)
+    keys = base.copy()
+    rng = np.random.default_rng(2)
+    at = rng.choice(keys.size, size=5000, replace=False)
+    keys[at] = base[rng.integers(0, keys.size, size=at.size)]       # duplicates
+    keys[rng.choice(keys.size, size=300, replace=False)] |= np.uint32(1 << 31)  # out of range
+    want, flags, _ = o.bitmap_sort(keys, 25)
+    assert flags == 3
+    bs.set_tuning(0, 0, path)
+    try:
+        got, st = _gpu_sort(keys, 25)
+    finally:
+        bs.set_tuning(0, 0, 0)
+    assert st.flags == 3 and st.count == want.size
+    np.testing.assert_array_equal(got[: want.size], want)
 
 
 @pytest.mark.parametrize("n,rb", [(500, 12), (200_000, 24), (60_000, 32)])
@@ -221,16 +270,17 @@ def test_side_stream_and_workspace_variant(o):
     np.testing.assert_array_equal(to_np(out2), want)
 
 
-@pytest.mark.parametrize("sb,tl", [(10, 12), (14, 13), (18, 14), (20, 12), (16, 14)])
-def test_tuning_knobs_keep_results(o, sb, tl):
+@pytest.mark.parametrize("sb,tl,path", [(10, 12, 1), (14, 13, 1), (18, 14, 1), (20, 12, 1), (16, 14, 1),
+                                        (15, 12, 2), (16, 13, 2), (18, 14, 2), (20, 14, 2), (0, 0, 2), (20, 15, 2), (16, 15, 1)])
+def test_tuning_knobs_keep_results(o, sb, tl, path):
     import paper_1312_0138_amd as bs
     keys = inputs.distinct_uniform(700_001, 24, 19)
     want, _, _ = o.bitmap_sort(keys, 24)
-    bs.set_tuning(sb, tl)
+    bs.set_tuning(sb, tl, path)
     try:
         got, st = _gpu_sort(keys, 24)
     finally:
-        bs.set_tuning(0, 0)
+        bs.set_tuning(0, 0, 0)
     assert st.count == keys.size
     np.testing.assert_array_equal(got, want)
 

@@ -38,18 +38,36 @@ def test_host_argument_checks(lib):
     assert E.bitsort_u32(fake, 100, 10, fake + 4, 0) == E.BITSORT_ERR_INVALID_ARG  # partial overlap
     assert E.bitsort_workspace_bytes(10, 3) == 0
     assert E.bitsort_workspace_bytes(10, 33) == 0
-    assert E.bitsort_set_tuning(9, 0) == E.BITSORT_ERR_INVALID_ARG
-    assert E.bitsort_set_tuning(0, 15) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_set_tuning(9, 0, 0) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_set_tuning(0, 16, 0) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_set_tuning(0, 0, 3) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_batch_u32(fake, fake, 0, fake, fake, 0, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_generate_u32(fake, 10, 1, 3, 0, 0) == E.BITSORT_ERR_TOO_LARGE
 
 
 def test_plan_shapes(lib):
-    rc, sb, tl, nb = _lib.bitsort_plan_info(1 << 26, 28)
-    assert rc == 0 and nb == 1 << (28 - sb) and 10 <= sb <= 20
-    rc, sb, tl, nb = _lib.bitsort_plan_info(1 << 24, 32)
-    assert rc == 0 and sb == 20 and nb == 4096
-    rc, sb, tl, nb = _lib.bitsort_plan_info(100, 10)
-    assert rc == 0 and nb == 1 and tl == 0  # single-workgroup path
+    rc, sb, tl, nb, ep = _lib.bitsort_plan_info(1 << 26, 28)
+    assert rc == 0 and nb == 1 << (28 - sb) and 10 <= sb <= 20 and ep == 2
+    rc, sb, tl, nb, ep = _lib.bitsort_plan_info(1 << 24, 32)
+    assert rc == 0 and sb == 20 and nb == 4096 and ep == 1
+    rc, sb, tl, nb, ep = _lib.bitsort_plan_info(100, 10)
+    assert rc == 0 and nb == 1 and tl == 0 and ep == 0  # single-workgroup path
     ws = _lib.bitsort_workspace_bytes(1 << 26, 28)
     assert ws >= 4 * (1 << 26)
+
+
+def test_single_hip_runtime_whatever_the_import_order():
+    """Loading the library before torch must not map a second HIP runtime
+    (torch bundles its own libamdhip64 under the same soname)."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_1312_0138_amd import _lib; _lib.lib()\n"
+        "import torch\n"
+        "maps = open('/proc/self/maps').read().splitlines()\n"
+        "libs = sorted({l.split()[-1] for l in maps if 'libamdhip64' in l})\n"
+        "print(len(libs), libs)\n"
+        "sys.exit(0 if len(libs) == 1 else 1)\n" % _lib.HERE.rsplit("/", 1)[0])
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert res.returncode == 0, res.stdout + res.stderr
