@@ -148,10 +148,22 @@ def bench_plain(args, workload):
         pool = max(2, min(128, -(-2 * MALL_BYTES // per)))
     bufs, n = make_plain_inputs(bs, torch, spec, workload, pool)
     out = torch.empty(n, dtype=torch.int32, device="cuda")
+    tuned = bs.autotune(n, rb, reps=3) if args.autotune else None
     plan = bs.plan_info(n, rb)
 
+    graphs = None
+    if args.graph:
+        # one captured graph per input buffer: replays allocate and launch nothing else
+        graphs = [bs.Graph.plain(b, rb, out) for b in bufs]
+
+    def step(i):
+        if graphs is not None:
+            graphs[i % len(graphs)].launch()
+        else:
+            bs.sort(bufs[i % len(bufs)], rb, out)
+
     for i in range(args.warmup):
-        bs.sort(bufs[i % len(bufs)], rb, out)
+        step(i)
     torch.cuda.synchronize()
 
     # Timed region 1 (the reported value): K back-to-back sorts, bracketed by
@@ -161,12 +173,16 @@ def bench_plain(args, workload):
     torch.cuda.synchronize()
     t0.record(stream)
     for i in range(args.steps):
-        bs.sort(bufs[i % len(bufs)], rb, out)
+        step(i)
     t1.record(stream)
     torch.cuda.synchronize()
     total_ms = t0.elapsed_time(t1)
-    st = bs.status()
-    assert st.flags == 0 and st.count == n, f"device status flags={st.flags} count={st.count}"
+    if graphs is not None:
+        (flags, count), = graphs[(args.steps - 1) % len(graphs)].status()
+    else:
+        st = bs.status()
+        flags, count = st.flags, st.count
+    assert flags == 0 and count == n, f"device status flags={flags} count={count}"
 
     # Timed region 2: the same K sorts with every kernel bracketed by HIP
     # events on its own stream (library profiling) and per-step events: the
@@ -178,7 +194,7 @@ def bench_plain(args, workload):
     torch.cuda.synchronize()
     for i in range(args.steps):
         starts[i].record(stream)
-        bs.sort(bufs[i % len(bufs)], rb, out)
+        bs.sort(bufs[i % len(bufs)], rb, out)  # eager calls: kernels timed by library events
         ends[i].record(stream)
     torch.cuda.synchronize()
     _lib.check(_lib.bitsort_profile_enable(False), "profile_enable")
@@ -213,6 +229,8 @@ def bench_plain(args, workload):
         "roofline_path": {"achieved": round(path_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                           "frac": round(path_gbps / HBM_PEAK_GBPS, 4), "algorithmic_bytes": ab["path"]},
         "kernels": kernels, "source_digest": digest, "tuning": args.tune or "default",
+        "launch": "hip-graph replay" if graphs is not None else "eager calls",
+        "autotuned": tuned,
     }
     if not args.no_cpu_baseline:
         keys_host = host_input(spec, workload, n)
@@ -260,16 +278,25 @@ def bench_batch(args):
     def run_batch():
         bs.sort_batch(keys, off_d, rb_d, out_b)
 
+    out_g = torch.empty_like(keys)
+    graph = bs.Graph.batch(keys, off_d, rb_d, out_g)
+
+    def run_graph():
+        graph.launch()
+
     def run_plain():
         for k, o, rb in views:
             bs.sort(k, rb, o)
 
+    if args.autotune:
+        res_tune = bs.autotune_batch(keys, off_d, rb_d, out_b, reps=2)
     for _ in range(args.warmup):
         run_batch()
+        run_graph()
         run_plain()
     torch.cuda.synchronize()
     res = {}
-    for name, fn in (("batched", run_batch), ("plain_loop", run_plain)):
+    for name, fn in (("batched", run_batch), ("batched_graph", run_graph), ("plain_loop", run_plain)):
         times = []
         for _ in range(max(3, args.steps // 10)):
             a = torch.cuda.Event(enable_timing=True)
@@ -285,7 +312,7 @@ def bench_batch(args):
                      "gkeys_per_s": round(total / (med / 1e3) / 1e9, 3)}
     flags, counts = bs.batch_status(count)
     assert not flags.any() and np.array_equal(counts, sizes.astype(np.uint64))
-    same = torch.equal(out_b, out_p)
+    same = torch.equal(out_b, out_p) and torch.equal(out_g, out_p)
     ab = sum(4 * int(n) + (1 << int(r)) // 8 + 4 * int(n) for n, r in zip(sizes, rbits))
     med_s = res["batched"]["median_ms"] / 1e3
     return {
@@ -294,7 +321,8 @@ def bench_batch(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": "batch", "segments": count, "total_keys": total,
                    "sizes": "log-uniform in [256, 2^20]", "range": "next power of two >= 4n"},
-        "batched": res["batched"], "plain_loop": res["plain_loop"],
+        "batched": res["batched"], "batched_graph": res["batched_graph"], "plain_loop": res["plain_loop"],
+        "autotuned": res_tune if args.autotune else None,
         "batched_over_plain": round(res["plain_loop"]["median_ms"] / res["batched"]["median_ms"], 3),
         "identical_results": bool(same),
         "roofline_path": {"achieved": round(ab / med_s / 1e9, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -335,6 +363,8 @@ def main():
     ap.add_argument("--pool", type=int, default=0, help="input buffers to rotate through (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", default="", help="slice_bits,tile_log2,emit_path (0 = library choice)")
+    ap.add_argument("--graph", action="store_true", help="time HIP-graph replays instead of eager calls")
+    ap.add_argument("--autotune", action="store_true", help="run the autotuner for the workload first")
     args = ap.parse_args()
     if args.tune:
         import paper_1312_0138_amd as bs

@@ -181,6 +181,57 @@ int bitsort_plan_info(uint64_t n, uint32_t range_bits, uint32_t *slice_bits, uin
                       uint32_t *buckets, uint32_t *emit_path);
 
 /*
+ * HIP graphs: the launches of one sort (plain or batch) captured once and
+ * replayed on any stream with bitsort_graph_launch().  The device buffers are
+ * fixed at creation; their contents may change between replays (a batch is
+ * re-planned on the device at every replay).  A graph owns its workspace, so
+ * replays allocate nothing.  Replays of one graph must not overlap in time.
+ *   bitsort_graph_status  synchronises `stream`, then copies the status of the
+ *                         last replay: one entry for a plain graph, up to
+ *                         num_segments for a batch graph.
+ */
+typedef struct bitsort_graph bitsort_graph_t;
+int bitsort_graph_create_u32(const uint32_t *keys, uint64_t n, uint32_t range_bits, uint32_t *out,
+                             bitsort_graph_t **graph);
+int bitsort_graph_create_batch_u32(const uint32_t *keys, const uint64_t *offsets, uint32_t num_segments,
+                                   const uint8_t *range_bits, uint32_t *out, uint64_t max_keys,
+                                   bitsort_graph_t **graph);
+int bitsort_graph_launch(bitsort_graph_t *graph, bitsort_stream_t stream);
+int bitsort_graph_status(bitsort_graph_t *graph, bitsort_stream_t stream, bitsort_status_t *status,
+                         uint32_t count);
+int bitsort_graph_destroy(bitsort_graph_t *graph);
+
+/*
+ * Autotuning.  bitsort_autotune_u32 times every valid (slice_bits,
+ * tile_log2, emit_path) on a generated input of n keys in [0, 2^range_bits)
+ * (reps timed runs each, HIP events on `stream`; it allocates and frees its
+ * own buffers) and makes the fastest the default for inputs with the same
+ * range_bits and ceil(log2 n).  bitsort_autotune_batch_u32 times the batch
+ * kernel's workgroup size (256/512/1024) and LDS slice bits (16..20) on the
+ * caller's batch (out is overwritten) and makes the fastest the default.
+ * Explicit bitsort_set_tuning values still take precedence.
+ * bitsort_tuning_save/load write and read the chosen settings as JSON lines
+ * keyed by GPU architecture and CU count (entries for another device are
+ * ignored on load); bitsort_tuning_clear forgets them.
+ */
+typedef struct bitsort_tuning {
+    uint32_t slice_bits;  /* plain and batch */
+    uint32_t tile_log2;   /* plain */
+    uint32_t emit_path;   /* plain: 1 LDS, 2 HBM bit-vector */
+    uint32_t batch_block; /* batch: workgroup size */
+    float ms;             /* measured time per call */
+} bitsort_tuning_t;
+
+int bitsort_autotune_u32(uint64_t n, uint32_t range_bits, int reps, bitsort_stream_t stream,
+                         bitsort_tuning_t *best);
+int bitsort_autotune_batch_u32(const uint32_t *keys, const uint64_t *offsets, uint32_t num_segments,
+                               const uint8_t *range_bits, uint32_t *out, uint64_t max_keys, int reps,
+                               bitsort_stream_t stream, bitsort_tuning_t *best);
+int bitsort_tuning_save(const char *path);
+int bitsort_tuning_load(const char *path, int *entries);
+int bitsort_tuning_clear(void);
+
+/*
  * Kernel timing for benchmarks.  While enabled, every kernel the library
  * launches is bracketed by two HIP events recorded on the launch's own
  * stream.  bitsort_profile_read() waits for those events and returns, per

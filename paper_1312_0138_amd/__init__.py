@@ -16,7 +16,8 @@ __all__ = [
     "sort", "status", "sort_batch", "batch_status", "generate", "debug_bitmap",
     "debug_prefix", "workspace_bytes", "sort_ws", "workspace_status", "set_tuning",
     "plan_info", "BitsortError", "Status", "STATUS_OUT_OF_RANGE", "STATUS_DUPLICATE",
-    "STATUS_BAD_SEGMENT",
+    "STATUS_BAD_SEGMENT", "Graph", "autotune", "autotune_batch", "tuning_save", "tuning_load",
+    "tuning_clear",
 ]
 
 
@@ -159,3 +160,79 @@ def plan_info(n: int, range_bits: int):
     rc, sb, tl, nb, ep = _lib.bitsort_plan_info(n, range_bits)
     _lib.check(rc, "bitsort_plan_info")
     return {"slice_bits": sb, "tile_log2": tl, "buckets": nb, "emit_path": EMIT_PATHS[ep]}
+
+
+class Graph:
+    """A captured sort (plain or batch) replayed with ``launch()``; the
+    tensors given at creation must stay alive and in place."""
+
+    def __init__(self, handle: int, segments: int, tensors):
+        self._h = handle
+        self.segments = segments
+        self._keep = tensors
+
+    @classmethod
+    def plain(cls, keys, range_bits: int, out):
+        _check_u32(keys, "keys")
+        _check_u32(out, "out")
+        rc, h = _lib.bitsort_graph_create_u32(keys.data_ptr(), keys.numel(), range_bits, out.data_ptr())
+        _lib.check(rc, "bitsort_graph_create_u32")
+        return cls(h, 0, (keys, out))
+
+    @classmethod
+    def batch(cls, keys, offsets, range_bits, out):
+        _check_u32(keys, "keys")
+        nseg = range_bits.numel()
+        rc, h = _lib.bitsort_graph_create_batch_u32(keys.data_ptr(), offsets.data_ptr(), nseg,
+                                                    range_bits.data_ptr(), out.data_ptr(), keys.numel())
+        _lib.check(rc, "bitsort_graph_create_batch_u32")
+        return cls(h, nseg, (keys, offsets, range_bits, out))
+
+    def launch(self, stream=None):
+        _lib.check(_lib.bitsort_graph_launch(self._h, _stream(stream)), "bitsort_graph_launch")
+
+    def status(self, stream=None):
+        count = self.segments or 1
+        rc, arr = _lib.bitsort_graph_status(self._h, _stream(stream), count)
+        _lib.check(rc, "bitsort_graph_status")
+        return [(arr[i].flags, arr[i].count) for i in range(count)]
+
+    def close(self):
+        if self._h:
+            _lib.check(_lib.bitsort_graph_destroy(self._h), "bitsort_graph_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+
+def autotune(n: int, range_bits: int, reps: int = 5, stream=None):
+    """Time every plain-path setting for (n, range_bits) and adopt the fastest."""
+    rc, t = _lib.bitsort_autotune_u32(n, range_bits, reps, _stream(stream))
+    _lib.check(rc, "bitsort_autotune_u32")
+    return {"slice_bits": t.slice_bits, "tile_log2": t.tile_log2, "emit_path": t.emit_path, "ms": t.ms}
+
+
+def autotune_batch(keys, offsets, range_bits, out, reps: int = 3, stream=None):
+    rc, t = _lib.bitsort_autotune_batch_u32(keys.data_ptr(), offsets.data_ptr(), range_bits.numel(),
+                                            range_bits.data_ptr(), out.data_ptr(), keys.numel(), reps,
+                                            _stream(stream))
+    _lib.check(rc, "bitsort_autotune_batch_u32")
+    return {"block": t.batch_block, "slice_bits": t.slice_bits, "ms": t.ms}
+
+
+def tuning_save(path: str) -> None:
+    _lib.check(_lib.bitsort_tuning_save(path), "bitsort_tuning_save")
+
+
+def tuning_load(path: str) -> int:
+    rc, n = _lib.bitsort_tuning_load(path)
+    _lib.check(rc, "bitsort_tuning_load")
+    return n
+
+
+def tuning_clear() -> None:
+    _lib.check(_lib.bitsort_tuning_clear(), "bitsort_tuning_clear")

@@ -34,6 +34,11 @@ class Status(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("_pad", ctypes.c_uint32), ("count", ctypes.c_uint64)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("slice_bits", ctypes.c_uint32), ("tile_log2", ctypes.c_uint32), ("emit_path", ctypes.c_uint32),
+                ("batch_block", ctypes.c_uint32), ("ms", ctypes.c_float)]
+
+
 class ProfileEntry(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
@@ -58,6 +63,16 @@ _SIGS = {
     "bitsort_set_tuning": (_c.c_int, [_u32, _u32, _u32]),
     "bitsort_plan_info": (_c.c_int, [_u64, _u32, _c.POINTER(_u32), _c.POINTER(_u32), _c.POINTER(_u32),
                                      _c.POINTER(_u32)]),
+    "bitsort_graph_create_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _c.POINTER(_vp)]),
+    "bitsort_graph_create_batch_u32": (_c.c_int, [_vp, _vp, _u32, _vp, _vp, _u64, _c.POINTER(_vp)]),
+    "bitsort_graph_launch": (_c.c_int, [_vp, _vp]),
+    "bitsort_graph_status": (_c.c_int, [_vp, _vp, _c.POINTER(Status), _u32]),
+    "bitsort_graph_destroy": (_c.c_int, [_vp]),
+    "bitsort_autotune_u32": (_c.c_int, [_u64, _u32, _c.c_int, _vp, _c.POINTER(Tuning)]),
+    "bitsort_autotune_batch_u32": (_c.c_int, [_vp, _vp, _u32, _vp, _vp, _u64, _c.c_int, _vp, _c.POINTER(Tuning)]),
+    "bitsort_tuning_save": (_c.c_int, [_c.c_char_p]),
+    "bitsort_tuning_load": (_c.c_int, [_c.c_char_p, _c.POINTER(_c.c_int)]),
+    "bitsort_tuning_clear": (_c.c_int, []),
     "bitsort_profile_enable": (_c.c_int, [_c.c_int]),
     "bitsort_profile_reset": (_c.c_int, []),
     "bitsort_profile_read": (_c.c_int, [_c.POINTER(ProfileEntry), _c.c_int, _c.POINTER(_c.c_int)]),
@@ -185,3 +200,59 @@ def bitsort_profile_read():
     n = ctypes.c_int()
     rc = lib().bitsort_profile_read(arr, 16, ctypes.byref(n))
     return rc, {arr[i].kernel.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(n.value, 16))}
+
+
+def bitsort_graph_create_u32(keys: int, n: int, range_bits: int, out: int):
+    g = _vp()
+    rc = lib().bitsort_graph_create_u32(keys, n, range_bits, out, ctypes.byref(g))
+    return rc, g.value
+
+
+def bitsort_graph_create_batch_u32(keys: int, offsets: int, num_segments: int, range_bits: int, out: int,
+                                   max_keys: int):
+    g = _vp()
+    rc = lib().bitsort_graph_create_batch_u32(keys, offsets, num_segments, range_bits, out, max_keys,
+                                              ctypes.byref(g))
+    return rc, g.value
+
+
+def bitsort_graph_launch(graph: int, stream: int) -> int:
+    return lib().bitsort_graph_launch(graph, stream)
+
+
+def bitsort_graph_status(graph: int, stream: int, count: int):
+    arr = (Status * max(count, 1))()
+    rc = lib().bitsort_graph_status(graph, stream, arr, count)
+    return rc, arr
+
+
+def bitsort_graph_destroy(graph: int) -> int:
+    return lib().bitsort_graph_destroy(graph)
+
+
+def bitsort_autotune_u32(n: int, range_bits: int, reps: int, stream: int):
+    t = Tuning()
+    rc = lib().bitsort_autotune_u32(n, range_bits, reps, stream, ctypes.byref(t))
+    return rc, t
+
+
+def bitsort_autotune_batch_u32(keys: int, offsets: int, num_segments: int, range_bits: int, out: int,
+                               max_keys: int, reps: int, stream: int):
+    t = Tuning()
+    rc = lib().bitsort_autotune_batch_u32(keys, offsets, num_segments, range_bits, out, max_keys, reps, stream,
+                                          ctypes.byref(t))
+    return rc, t
+
+
+def bitsort_tuning_save(path: str) -> int:
+    return lib().bitsort_tuning_save(path.encode())
+
+
+def bitsort_tuning_load(path: str):
+    n = ctypes.c_int()
+    rc = lib().bitsort_tuning_load(path.encode(), ctypes.byref(n))
+    return rc, n.value
+
+
+def bitsort_tuning_clear() -> int:
+    return lib().bitsort_tuning_clear()

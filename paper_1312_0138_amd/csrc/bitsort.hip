@@ -47,6 +47,9 @@
 #include <mutex>
 #include <utility>
 #include <vector>
+#include <cstdio>
+#include <functional>
+#include <string>
 
 #include "bitsort.h"
 #include "bitsort_device.h"
@@ -65,7 +68,6 @@ constexpr uint32_t kDirectBlock = 1024;
 constexpr uint64_t kDirectMaxN = 8192;        // single-workgroup path below this
 constexpr uint32_t kHeaderBytes = 256;        // status + scratch header in LDS / workspace
 constexpr uint32_t kStageMax = 8192;
-constexpr uint32_t kBatchBlock = 1024;
 constexpr uint32_t kBatchSliceBits = 20;
 constexpr uint32_t kChunkWords = 1024;        // words per k_emit workgroup
 constexpr uint32_t kEmitBlock = 256;
@@ -812,6 +814,7 @@ struct Plan {
 std::atomic<uint32_t> g_tune_sb{0};
 std::atomic<uint32_t> g_tune_tile{0};
 std::atomic<uint32_t> g_tune_path{0};  // 0 auto, 1 emit from LDS, 2 through the HBM bit-vector
+std::mutex g_tune_mu;                   // guards the autotuned tables
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
@@ -828,9 +831,33 @@ size_t slice_lds_bytes(uint32_t sb, uint32_t stage_cap) {
   return kHeaderBytes + round_up4(slice_words) * 4u + static_cast<size_t>(stage_cap) * 4u;
 }
 
-void make_plan(uint64_t n, uint32_t rb, Plan* p) {
+// Plain-path settings chosen by bitsort_autotune_u32 (or loaded from a
+// tuning cache), per (range_bits, ceil(log2 n)).
+struct PlainTuning {
+  uint32_t slice_bits = 0, tile_log2 = 0, emit_path = 0;
+  float ms = 0.f;
+};
+std::map<std::pair<uint32_t, uint32_t>, PlainTuning> g_plain_tuned;  // guarded by g_tune_mu
+
+uint32_t ceil_log2(uint64_t n) {
+  uint32_t l = 0;
+  while ((1ull << l) < n) ++l;
+  return l;
+}
+
+// force != nullptr: use exactly these settings (autotuner candidates),
+// ignoring the explicit knobs and the tuned table.
+void make_plan(uint64_t n, uint32_t rb, Plan* p, const PlainTuning* force = nullptr) {
   *p = Plan();
   p->rb = rb;
+  PlainTuning tuned;
+  if (force != nullptr) {
+    tuned = *force;
+  } else {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_plain_tuned.find({rb, ceil_log2(n)});
+    if (it != g_plain_tuned.end()) tuned = it->second;
+  }
   if (rb <= kMinSliceBits || (rb <= kMaxSliceBits && n <= kDirectMaxN)) {
     p->direct = true;
     p->sb = rb;
@@ -838,14 +865,16 @@ void make_plan(uint64_t n, uint32_t rb, Plan* p) {
     p->bytes = kHeaderBytes;
   } else {
     p->direct = false;
-    uint32_t sb = g_tune_sb.load();
+    uint32_t sb = force ? 0u : g_tune_sb.load();
+    if (sb == 0) sb = tuned.slice_bits;
     if (sb == 0) sb = rb > 8 ? rb - 8 : rb;  // aim at 256 slices
     const uint32_t lo = std::max<uint32_t>(std::min(rb, kMinSliceBits), rb > kMaxBucketsLog2 ? rb - kMaxBucketsLog2 : 0);
     sb = std::max(sb, lo);
     sb = std::min({sb, kMaxSliceBits, rb});
     p->sb = sb;
     p->nb = 1u << (rb - sb);
-    uint32_t tl = g_tune_tile.load();
+    uint32_t tl = force ? 0u : g_tune_tile.load();
+    if (tl == 0) tl = tuned.tile_log2;
     if (tl == 0) tl = n >= (1ull << 22) ? 14 : 12;
     tl = std::min<uint32_t>(std::max<uint32_t>(tl, 12), 15);
     p->tile_log2 = tl;
@@ -858,7 +887,8 @@ void make_plan(uint64_t n, uint32_t rb, Plan* p) {
     // Emit through an HBM bit-vector when it is small next to the keys
     // (R/8 <= 2n): the bit-vector round trip costs 2R/8 bytes, and in return
     // the emission runs at full occupancy instead of beside a 2^sb-bit slice.
-    const uint32_t path = g_tune_path.load();
+    uint32_t path = force ? 0u : g_tune_path.load();
+    if (path == 0) path = tuned.emit_path;
     const uint64_t bv_bytes = (1ull << rb) / 8u;
     if ((1u << (sb - 5)) >= kChunkWords && (path == 2 || (path == 0 && bv_bytes <= 2 * n))) {
       p->via_bitvec = true;
@@ -904,7 +934,9 @@ int init_kernels() {
     set_lds_attr(k_partition<1024, 32>, kLdsBytes);
     set_lds_attr(k_slice<kSliceBlock, kSliceUnroll>, kLdsBytes);
     set_lds_attr(k_direct<kDirectBlock>, kLdsBytes);
-    set_lds_attr(k_batch_run<kBatchBlock>, kLdsBytes);
+    set_lds_attr(k_batch_run<256>, kLdsBytes);
+    set_lds_attr(k_batch_run<512>, kLdsBytes);
+    set_lds_attr(k_batch_run<1024>, kLdsBytes);
   });
   return g_attr_err == hipSuccess ? BITSORT_OK : BITSORT_ERR_HIP;
 }
@@ -923,6 +955,7 @@ struct PendingTiming {
   hipEvent_t start, stop;
 };
 std::atomic<bool> g_prof_on{false};
+thread_local bool t_capturing = false;  // enqueueing into a graph capture: no timing events
 std::mutex g_prof_mu;
 std::vector<PendingTiming> g_prof_pending;
 uint64_t g_prof_launches[kKCount] = {};
@@ -934,7 +967,7 @@ struct LaunchTimer {
   hipStream_t stream;
   hipEvent_t start = nullptr;
   LaunchTimer(int k, hipStream_t s) : kernel(k), stream(s) {
-    if (!g_prof_on.load(std::memory_order_relaxed)) return;
+    if (!g_prof_on.load(std::memory_order_relaxed) || t_capturing) return;
     if (hipEventCreate(&start) != hipSuccess || hipEventRecord(start, stream) != hipSuccess) start = nullptr;
   }
   ~LaunchTimer() {
@@ -1015,6 +1048,89 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
   LaunchTimer timer(kKFinish, stream);
   hipLaunchKernelGGL((k_finish<kSliceBlock>), dim3(1), dim3(kSliceBlock), 0, stream, n, p.nb, info, status, out);
   return launch_status();
+}
+
+// Batch tuning: workgroup size of k_batch_run and bits per LDS slice.
+struct BatchTuning {
+  uint32_t block = 1024;
+  uint32_t slice_bits = kBatchSliceBits;
+};
+BatchTuning g_batch_tuned;           // set by bitsort_autotune_batch_u32 / the tuning cache
+std::atomic<uint32_t> g_batch_block{0};
+std::atomic<uint32_t> g_batch_sb{0};
+
+BatchTuning batch_tuning() {
+  BatchTuning t;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    t = g_batch_tuned;
+  }
+  if (g_batch_block.load()) t.block = g_batch_block.load();
+  if (g_batch_sb.load()) t.slice_bits = g_batch_sb.load();
+  return t;
+}
+
+int check_batch_args(const uint32_t* keys, const uint64_t* offsets, uint32_t num_segments,
+                     const uint8_t* range_bits, const uint32_t* out, uint64_t max_keys) {
+  if (num_segments == 0 || num_segments > BITSORT_BATCH_MAX_SEGMENTS) return BITSORT_ERR_INVALID_ARG;
+  if (keys == nullptr || offsets == nullptr || range_bits == nullptr || out == nullptr) return BITSORT_ERR_INVALID_ARG;
+  if (max_keys >= (1ull << 40)) return BITSORT_ERR_TOO_LARGE;
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(keys), a1 = a0 + 4 * max_keys;
+  const uintptr_t b0 = reinterpret_cast<uintptr_t>(out), b1 = b0 + 4 * max_keys;
+  if (max_keys > 0 && a0 < b1 && b0 < a1) return BITSORT_ERR_INVALID_ARG;
+  return BITSORT_OK;
+}
+
+size_t batch_workspace_bytes(uint32_t num_segments, const BatchTuning& t) {
+  const uint64_t max_items = static_cast<uint64_t>(num_segments) << (kMaxBatchRangeBits - t.slice_bits);
+  const size_t off_items = align256(kHeaderBytes + sizeof(SegStatus) * num_segments);
+  return align256(off_items + sizeof(uint2) * max_items);
+}
+
+template <int BLOCK>
+int launch_batch_run(const uint32_t* keys, const uint64_t* offsets, const uint8_t* range_bits, uint32_t sbb,
+                     const uint2* items, uint32_t* counter, uint32_t* out, SegStatus* st, uint64_t max_items,
+                     hipStream_t s) {
+  const uint32_t stage_cap = stage_cap_for(sbb);
+  const size_t lds = slice_lds_bytes(sbb, stage_cap);
+  int cus = 256, dev = 0, per_cu = 1;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_run<BLOCK>, BLOCK, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const uint64_t grid = std::min<uint64_t>(static_cast<uint64_t>(cus) * per_cu, max_items);
+  LaunchTimer timer(kKBatchRun, s);
+  hipLaunchKernelGGL(k_batch_run<BLOCK>, dim3(static_cast<uint32_t>(grid)), dim3(BLOCK), lds, s, keys, offsets,
+                     range_bits, sbb, stage_cap, items, counter, out, st);
+  return launch_status();
+}
+
+// Enqueue the batch: plan on the device, then the persistent item loop.
+int run_batch(const uint32_t* keys, const uint64_t* offsets, uint32_t num_segments, const uint8_t* range_bits,
+              uint32_t* out, uint64_t max_keys, void* ws, hipStream_t s, const BatchTuning& t) {
+  const uint32_t sbb = t.slice_bits;
+  const uint64_t max_items = static_cast<uint64_t>(num_segments) << (kMaxBatchRangeBits - sbb);
+  const size_t off_items = align256(kHeaderBytes + sizeof(SegStatus) * num_segments);
+  char* base = static_cast<char*>(ws);
+  uint32_t* counter = reinterpret_cast<uint32_t*>(base);
+  SegStatus* st = reinterpret_cast<SegStatus*>(base + kHeaderBytes);
+  uint2* items = reinterpret_cast<uint2*>(base + off_items);
+  int rc;
+  {
+    LaunchTimer timer(kKBatchPlan, s);
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, s, offsets, range_bits, num_segments, max_keys, sbb,
+                       items, counter, st);
+    rc = launch_status();
+  }
+  if (rc != BITSORT_OK) return rc;
+  switch (t.block) {
+    case 256:
+      return launch_batch_run<256>(keys, offsets, range_bits, sbb, items, counter, out, st, max_items, s);
+    case 512:
+      return launch_batch_run<512>(keys, offsets, range_bits, sbb, items, counter, out, st, max_items, s);
+    default:
+      return launch_batch_run<1024>(keys, offsets, range_bits, sbb, items, counter, out, st, max_items, s);
+  }
 }
 
 // Library-owned workspaces, one per (device, stream).
@@ -1202,48 +1318,19 @@ int bitsort_debug_prefix_u32(const uint32_t* keys, uint64_t n, uint32_t range_bi
 
 int bitsort_batch_u32(const uint32_t* keys, const uint64_t* offsets, uint32_t num_segments,
                       const uint8_t* range_bits, uint32_t* out, uint64_t max_keys, bitsort_stream_t stream) {
-  if (num_segments == 0 || num_segments > BITSORT_BATCH_MAX_SEGMENTS) return BITSORT_ERR_INVALID_ARG;
-  if (keys == nullptr || offsets == nullptr || range_bits == nullptr || out == nullptr) return BITSORT_ERR_INVALID_ARG;
-  if (max_keys >= (1ull << 40)) return BITSORT_ERR_TOO_LARGE;
-  {
-    const uintptr_t a0 = reinterpret_cast<uintptr_t>(keys), a1 = a0 + 4 * max_keys;
-    const uintptr_t b0 = reinterpret_cast<uintptr_t>(out), b1 = b0 + 4 * max_keys;
-    if (max_keys > 0 && a0 < b1 && b0 < a1) return BITSORT_ERR_INVALID_ARG;
-  }
-  int rc = init_kernels();
+  int rc = check_batch_args(keys, offsets, num_segments, range_bits, out, max_keys);
+  if (rc != BITSORT_OK) return rc;
+  rc = init_kernels();
   if (rc != BITSORT_OK) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const uint32_t sbb = kBatchSliceBits;
-  const uint64_t max_items = static_cast<uint64_t>(num_segments) << (kMaxBatchRangeBits - sbb);
-  const size_t off_status = kHeaderBytes;
-  const size_t off_items = align256(off_status + sizeof(SegStatus) * num_segments);
-  const size_t bytes = align256(off_items + sizeof(uint2) * max_items);
+  const BatchTuning t = batch_tuning();
+  const size_t bytes = batch_workspace_bytes(num_segments, t);
   std::lock_guard<std::mutex> lock(g_mu);
   StreamCtx& c = ctx_for(stream);
   rc = grow(&c.batch_ws, &c.batch_bytes, bytes, s);
   if (rc != BITSORT_OK) return rc;
   c.batch_segments = num_segments;
-  char* base = static_cast<char*>(c.batch_ws);
-  uint32_t* counter = reinterpret_cast<uint32_t*>(base);
-  SegStatus* st = reinterpret_cast<SegStatus*>(base + off_status);
-  uint2* items = reinterpret_cast<uint2*>(base + off_items);
-  {
-    LaunchTimer timer(kKBatchPlan, s);
-    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, s, offsets, range_bits, num_segments, max_keys, sbb,
-                       items, counter, st);
-    rc = launch_status();
-  }
-  if (rc != BITSORT_OK) return rc;
-  const uint32_t stage_cap = stage_cap_for(sbb);
-  const size_t lds = slice_lds_bytes(sbb, stage_cap);
-  int cus = 256;
-  int dev = 0;
-  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const uint64_t grid = std::min<uint64_t>(static_cast<uint64_t>(cus), max_items);
-  LaunchTimer timer(kKBatchRun, s);
-  hipLaunchKernelGGL(k_batch_run<kBatchBlock>, dim3(static_cast<uint32_t>(grid)), dim3(kBatchBlock), lds, s, keys,
-                     offsets, range_bits, sbb, stage_cap, items, counter, out, st);
-  return launch_status();
+  return run_batch(keys, offsets, num_segments, range_bits, out, max_keys, c.batch_ws, s, t);
 }
 
 int bitsort_batch_status(bitsort_stream_t stream, bitsort_status_t* status, uint32_t num_segments) {
@@ -1262,6 +1349,304 @@ int bitsort_batch_status(bitsort_stream_t stream, bitsort_status_t* status, uint
   if (hipMemcpy(status, static_cast<char*>(ws) + kHeaderBytes, sizeof(SegStatus) * num_segments,
                 hipMemcpyDeviceToHost) != hipSuccess)
     return BITSORT_ERR_HIP;
+  return BITSORT_OK;
+}
+
+// ---- graphs -------------------------------------------------------------------
+
+struct bitsort_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* ws = nullptr;
+  bool batch = false;
+  uint32_t segments = 0;
+  int device = 0;
+};
+
+static int capture(bitsort_graph* g, const std::function<int(hipStream_t)>& enqueue) {
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return BITSORT_ERR_HIP;
+  int rc = BITSORT_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rc = BITSORT_ERR_HIP;
+  } else {
+    t_capturing = true;
+    rc = enqueue(cs);
+    t_capturing = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (rc == BITSORT_OK && e != hipSuccess) rc = BITSORT_ERR_HIP;
+    if (rc == BITSORT_OK) {
+      g->graph = graph;
+      if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) rc = BITSORT_ERR_HIP;
+    } else if (graph != nullptr) {
+      (void)hipGraphDestroy(graph);
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  return rc;
+}
+
+int bitsort_graph_create_u32(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32_t* out,
+                             bitsort_graph_t** graph) {
+  if (graph == nullptr) return BITSORT_ERR_INVALID_ARG;
+  *graph = nullptr;
+  int rc = check_args(keys, n, range_bits, out);
+  if (rc != BITSORT_OK) return rc;
+  if (n == 0) return BITSORT_ERR_INVALID_ARG;
+  rc = init_kernels();
+  if (rc != BITSORT_OK) return rc;
+  Plan p;
+  make_plan(n, range_bits, &p);
+  auto* g = new bitsort_graph();
+  (void)hipGetDevice(&g->device);
+  if (hipMalloc(&g->ws, p.bytes) != hipSuccess) {
+    delete g;
+    return BITSORT_ERR_NO_MEMORY;
+  }
+  rc = capture(g, [&](hipStream_t cs) { return run_plain(p, keys, n, out, g->ws, cs, kEmit, nullptr, nullptr); });
+  if (rc != BITSORT_OK) {
+    bitsort_graph_destroy(g);
+    return rc;
+  }
+  *graph = g;
+  return BITSORT_OK;
+}
+
+int bitsort_graph_create_batch_u32(const uint32_t* keys, const uint64_t* offsets, uint32_t num_segments,
+                                   const uint8_t* range_bits, uint32_t* out, uint64_t max_keys,
+                                   bitsort_graph_t** graph) {
+  if (graph == nullptr) return BITSORT_ERR_INVALID_ARG;
+  *graph = nullptr;
+  int rc = check_batch_args(keys, offsets, num_segments, range_bits, out, max_keys);
+  if (rc != BITSORT_OK) return rc;
+  rc = init_kernels();
+  if (rc != BITSORT_OK) return rc;
+  const BatchTuning t = batch_tuning();
+  auto* g = new bitsort_graph();
+  g->batch = true;
+  g->segments = num_segments;
+  (void)hipGetDevice(&g->device);
+  if (hipMalloc(&g->ws, batch_workspace_bytes(num_segments, t)) != hipSuccess) {
+    delete g;
+    return BITSORT_ERR_NO_MEMORY;
+  }
+  rc = capture(g, [&](hipStream_t cs) {
+    return run_batch(keys, offsets, num_segments, range_bits, out, max_keys, g->ws, cs, t);
+  });
+  if (rc != BITSORT_OK) {
+    bitsort_graph_destroy(g);
+    return rc;
+  }
+  *graph = g;
+  return BITSORT_OK;
+}
+
+int bitsort_graph_launch(bitsort_graph_t* graph, bitsort_stream_t stream) {
+  if (graph == nullptr || graph->exec == nullptr) return BITSORT_ERR_INVALID_ARG;
+  return hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? BITSORT_OK : BITSORT_ERR_HIP;
+}
+
+int bitsort_graph_status(bitsort_graph_t* graph, bitsort_stream_t stream, bitsort_status_t* status,
+                         uint32_t count) {
+  if (graph == nullptr || status == nullptr) return BITSORT_ERR_INVALID_ARG;
+  if (count > (graph->batch ? graph->segments : 1u)) return BITSORT_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return BITSORT_ERR_HIP;
+  if (count == 0) return BITSORT_OK;
+  const char* src = static_cast<const char*>(graph->ws) + (graph->batch ? kHeaderBytes : 0);
+  static_assert(sizeof(Status) == sizeof(bitsort_status_t), "status layouts must match");
+  if (hipMemcpy(status, src, sizeof(bitsort_status_t) * count, hipMemcpyDeviceToHost) != hipSuccess)
+    return BITSORT_ERR_HIP;
+  if (!graph->batch) status[0]._pad = 0;
+  return BITSORT_OK;
+}
+
+int bitsort_graph_destroy(bitsort_graph_t* graph) {
+  if (graph == nullptr) return BITSORT_OK;
+  int rc = BITSORT_OK;
+  if (graph->exec && hipGraphExecDestroy(graph->exec) != hipSuccess) rc = BITSORT_ERR_HIP;
+  if (graph->graph && hipGraphDestroy(graph->graph) != hipSuccess) rc = BITSORT_ERR_HIP;
+  if (graph->ws && hipFree(graph->ws) != hipSuccess) rc = BITSORT_ERR_HIP;
+  delete graph;
+  return rc;
+}
+
+// ---- autotuning -----------------------------------------------------------------
+
+static float time_ms(const std::function<int()>& run, int reps, hipStream_t s, int* rc) {
+  hipEvent_t a = nullptr, b = nullptr;
+  float ms = -1.f;
+  *rc = BITSORT_OK;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    *rc = BITSORT_ERR_HIP;
+  } else {
+    *rc = run();  // warm-up (also grows workspaces)
+    if (*rc == BITSORT_OK && hipEventRecord(a, s) == hipSuccess) {
+      for (int r = 0; r < reps && *rc == BITSORT_OK; ++r) *rc = run();
+      if (*rc == BITSORT_OK && hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess &&
+          hipEventElapsedTime(&ms, a, b) == hipSuccess)
+        ms /= static_cast<float>(reps);
+      else if (*rc == BITSORT_OK)
+        *rc = BITSORT_ERR_HIP;
+    }
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  return ms;
+}
+
+int bitsort_autotune_u32(uint64_t n, uint32_t range_bits, int reps, bitsort_stream_t stream,
+                         bitsort_tuning_t* best) {
+  if (best == nullptr || reps < 1 || range_bits > 32 || n == 0 || n > (1ull << range_bits) || n >= (1ull << 32))
+    return BITSORT_ERR_INVALID_ARG;
+  int rc = init_kernels();
+  if (rc != BITSORT_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Plan base_plan;
+  make_plan(n, range_bits, &base_plan);
+  *best = bitsort_tuning_t{};
+  if (base_plan.direct) return BITSORT_OK;  // nothing to choose
+  uint32_t *keys = nullptr, *out = nullptr;
+  if (hipMalloc(&keys, 4 * n) != hipSuccess) return BITSORT_ERR_NO_MEMORY;
+  if (hipMalloc(&out, 4 * n) != hipSuccess) {
+    (void)hipFree(keys);
+    return BITSORT_ERR_NO_MEMORY;
+  }
+  rc = bitsort_generate_u32(keys, 0, n, range_bits, 0x5EEDull + range_bits, stream);
+  // Candidates: the five widest slice sizes the fan-out limit allows, every
+  // tile size, both emit paths.
+  const uint32_t sb_lo = std::max<uint32_t>(kMinSliceBits, range_bits > kMaxBucketsLog2 ? range_bits - kMaxBucketsLog2 : 0);
+  const uint32_t sb_hi = std::min(kMaxSliceBits, range_bits);
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  float best_ms = 1e30f;
+  for (uint32_t sb = std::max(sb_lo, sb_hi >= 4 ? sb_hi - 4 : 0); sb <= sb_hi && rc == BITSORT_OK; ++sb) {
+    for (uint32_t tl = 12; tl <= 15 && rc == BITSORT_OK; ++tl) {
+      for (uint32_t path = 1; path <= 2 && rc == BITSORT_OK; ++path) {
+        const PlainTuning cand{sb, tl, path, 0.f};
+        Plan p;
+        make_plan(n, range_bits, &p, &cand);
+        if (p.direct || p.sb != sb || p.tile_log2 != tl || (path == 2) != p.via_bitvec) continue;
+        rc = grow(&ws, &ws_bytes, p.bytes, s);
+        if (rc != BITSORT_OK) break;
+        const float ms = time_ms([&] { return run_plain(p, keys, n, out, ws, s, kEmit, nullptr, nullptr); },
+                                 reps, s, &rc);
+        if (rc == BITSORT_OK && ms >= 0.f && ms < best_ms) {
+          best_ms = ms;
+          *best = bitsort_tuning_t{sb, tl, path, 0, ms};
+        }
+      }
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  if (ws) (void)hipFree(ws);
+  (void)hipFree(keys);
+  (void)hipFree(out);
+  if (rc == BITSORT_OK && best->slice_bits != 0) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_plain_tuned[{range_bits, ceil_log2(n)}] = PlainTuning{best->slice_bits, best->tile_log2, best->emit_path, best->ms};
+  }
+  return rc;
+}
+
+int bitsort_autotune_batch_u32(const uint32_t* keys, const uint64_t* offsets, uint32_t num_segments,
+                               const uint8_t* range_bits, uint32_t* out, uint64_t max_keys, int reps,
+                               bitsort_stream_t stream, bitsort_tuning_t* best) {
+  if (best == nullptr || reps < 1) return BITSORT_ERR_INVALID_ARG;
+  int rc = check_batch_args(keys, offsets, num_segments, range_bits, out, max_keys);
+  if (rc != BITSORT_OK) return rc;
+  rc = init_kernels();
+  if (rc != BITSORT_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  *best = bitsort_tuning_t{};
+  float best_ms = 1e30f;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  for (uint32_t block : {256u, 512u, 1024u}) {
+    for (uint32_t sbb = 16; sbb <= kBatchSliceBits && rc == BITSORT_OK; ++sbb) {
+      const BatchTuning t{block, sbb};
+      rc = grow(&ws, &ws_bytes, batch_workspace_bytes(num_segments, t), s);
+      if (rc != BITSORT_OK) break;
+      const float ms = time_ms([&] {
+        return run_batch(keys, offsets, num_segments, range_bits, out, max_keys, ws, s, t);
+      }, reps, s, &rc);
+      if (rc == BITSORT_OK && ms >= 0.f && ms < best_ms) {
+        best_ms = ms;
+        *best = bitsort_tuning_t{sbb, 0, 0, block, ms};
+      }
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  if (ws) (void)hipFree(ws);
+  if (rc == BITSORT_OK && best->batch_block != 0) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_batch_tuned = BatchTuning{best->batch_block, best->slice_bits};
+  }
+  return rc;
+}
+
+static std::string device_key() {
+  int dev = 0, cus = 0;
+  hipDeviceProp_t prop{};
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+  }
+  return arch + ":" + std::to_string(cus);
+}
+
+int bitsort_tuning_save(const char* path) {
+  if (path == nullptr) return BITSORT_ERR_INVALID_ARG;
+  FILE* f = std::fopen(path, "w");
+  if (f == nullptr) return BITSORT_ERR_INVALID_ARG;
+  const std::string dk = device_key();
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  for (const auto& kv : g_plain_tuned)
+    std::fprintf(f, "{\"device\": \"%s\", \"kind\": \"plain\", \"range_bits\": %u, \"log2n\": %u, "
+                    "\"slice_bits\": %u, \"tile_log2\": %u, \"emit_path\": %u, \"ms\": %.5f}\n",
+                 dk.c_str(), kv.first.first, kv.first.second, kv.second.slice_bits, kv.second.tile_log2,
+                 kv.second.emit_path, kv.second.ms);
+  std::fprintf(f, "{\"device\": \"%s\", \"kind\": \"batch\", \"block\": %u, \"slice_bits\": %u}\n", dk.c_str(),
+               g_batch_tuned.block, g_batch_tuned.slice_bits);
+  return std::fclose(f) == 0 ? BITSORT_OK : BITSORT_ERR_INVALID_ARG;
+}
+
+int bitsort_tuning_load(const char* path, int* entries) {
+  if (path == nullptr) return BITSORT_ERR_INVALID_ARG;
+  FILE* f = std::fopen(path, "r");
+  if (f == nullptr) return BITSORT_ERR_INVALID_ARG;
+  const std::string dk = device_key();
+  char line[512], dev[128];
+  int count = 0;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  while (std::fgets(line, sizeof line, f)) {
+    unsigned rb, l2, sb, tl, ep, block;
+    float ms;
+    if (std::sscanf(line, "{\"device\": \"%127[^\"]\", \"kind\": \"plain\", \"range_bits\": %u, \"log2n\": %u, "
+                          "\"slice_bits\": %u, \"tile_log2\": %u, \"emit_path\": %u, \"ms\": %f}",
+                    dev, &rb, &l2, &sb, &tl, &ep, &ms) == 7) {
+      if (dk != dev || rb > 32 || sb < kMinSliceBits || sb > kMaxSliceBits || tl < 12 || tl > 15 || ep > 2) continue;
+      g_plain_tuned[{rb, l2}] = PlainTuning{sb, tl, ep, ms};
+      ++count;
+    } else if (std::sscanf(line, "{\"device\": \"%127[^\"]\", \"kind\": \"batch\", \"block\": %u, \"slice_bits\": %u}",
+                           dev, &block, &sb) == 3) {
+      if (dk != dev || (block != 256 && block != 512 && block != 1024) || sb < 16 || sb > kBatchSliceBits) continue;
+      g_batch_tuned = BatchTuning{block, sb};
+      ++count;
+    }
+  }
+  std::fclose(f);
+  if (entries) *entries = count;
+  return BITSORT_OK;
+}
+
+int bitsort_tuning_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_plain_tuned.clear();
+  g_batch_tuned = BatchTuning{};
   return BITSORT_OK;
 }
 

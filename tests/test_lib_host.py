@@ -71,3 +71,29 @@ def test_single_hip_runtime_whatever_the_import_order():
         "sys.exit(0 if len(libs) == 1 else 1)\n" % _lib.HERE.rsplit("/", 1)[0])
     res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert res.returncode == 0, res.stdout + res.stderr
+
+
+def test_tuning_cache_plumbing(lib, tmp_path):
+    """A cache line for this device key is adopted by the planner; lines for
+    another device or with out-of-range values are ignored."""
+    path = tmp_path / "t.jsonl"
+    _lib.bitsort_tuning_clear()
+    assert _lib.bitsort_tuning_save(str(path)) == 0
+    first = path.read_text().splitlines()[0]
+    dev = first.split('"device": "')[1].split('"')[0]
+    path.write_text(
+        f'{{"device": "{dev}", "kind": "plain", "range_bits": 27, "log2n": 25, "slice_bits": 17, '
+        f'"tile_log2": 13, "emit_path": 1, "ms": 0.1}}\n'
+        f'{{"device": "other:1", "kind": "plain", "range_bits": 27, "log2n": 24, "slice_bits": 18, '
+        f'"tile_log2": 13, "emit_path": 1, "ms": 0.1}}\n'
+        f'{{"device": "{dev}", "kind": "plain", "range_bits": 27, "log2n": 23, "slice_bits": 99, '
+        f'"tile_log2": 13, "emit_path": 1, "ms": 0.1}}\n')
+    rc, n = _lib.bitsort_tuning_load(str(path))
+    assert rc == 0 and n == 1
+    rc, sb, tl, nb, ep = _lib.bitsort_plan_info(1 << 25, 27)
+    assert (sb, tl, ep) == (17, 13, 1)
+    rc, sb2, tl2, nb2, ep2 = _lib.bitsort_plan_info(1 << 24, 27)
+    assert sb2 != 17 or tl2 != 13
+    _lib.bitsort_tuning_clear()
+    rc, sb3, tl3, nb3, ep3 = _lib.bitsort_plan_info(1 << 25, 27)
+    assert (sb3, tl3) != (17, 13)
