@@ -18,6 +18,10 @@ Workloads (default: plain-uniform):
   plain-sparse    2^24 distinct keys in [0, 2^32)
   batch           4096 arrays, sizes log-uniform in [256, 2^20], range the
                   power of two >= 4n: one batched launch vs 4096 plain launches
+  serve           20,000 sort requests, sizes log-uniform in [2^10, 2^24],
+                  range the power of two >= 4n, Poisson arrivals at 70% of the
+                  loop's measured burst throughput, 64 GiB device budget; one
+                  step is the whole trace (keys/s, p50/p99 latency)
 """
 from __future__ import annotations
 
@@ -330,6 +334,93 @@ def bench_batch(args):
     }
 
 
+def serve_cpu_baseline(trace, results, budget_s: float = 20.0, max_keys: int = 1 << 24):
+    """The oracle sorts a seeded sample of the trace's requests (inputs
+    regenerated on the host); its digests must equal the served ones."""
+    import numpy as np
+
+    import oracle
+    from paper_1312_0138_amd import inputs, serve
+    o = oracle.default()
+    rng = np.random.default_rng(0xB5)
+    keys_done, t_sort, checked, bad = 0, 0.0, 0, []
+    t_start = time.perf_counter()
+    for i in rng.permutation(len(trace)):
+        n, rb, seed = int(trace["n"][i]), int(trace["range_bits"][i]), int(trace["seed"][i])
+        if time.perf_counter() - t_start > budget_s:
+            break
+        if keys_done + n > max_keys:
+            continue
+        keys = inputs.distinct_uniform(n, rb, seed)
+        t0 = time.perf_counter()
+        want, flags, _ = o.bitmap_sort(keys, rb)
+        t_sort += time.perf_counter() - t0
+        keys_done += n
+        checked += 1
+        if flags != 0 or serve.host_digest(want) != int(results["digest"][i]):
+            bad.append(int(i))
+    return keys_done / t_sort / 1e9, checked, keys_done, t_sort, bad
+
+
+def bench_serve(args):
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1312_0138_amd import inputs, serve
+
+    torch.cuda.set_device(0)
+    count, lo, hi, budget = args.serve_requests, 1 << 10, 1 << 24, 64 << 30
+    streams = args.serve_streams
+    seed = inputs.config_seed(5, 0)
+    # burst calibration on a 512-request sample of the same size distribution
+    cal = serve.make_trace(512, lo, hi, math.inf, inputs.config_seed(5, 1))
+    serve.run(cal[:64], budget, streams=streams)
+    _, st_cal = serve.run(cal, budget, streams=streams)
+    t_burst = st_cal["keys"] / st_cal["makespan_s"]
+    _, st_one = serve.run(cal, budget, streams=1, max_batch_requests=1)
+    t_one = st_one["keys"] / st_one["makespan_s"]
+    trace = serve.make_trace(count, lo, hi, 1.0, seed)
+    rate = 0.7 * t_burst / float(trace["n"].mean())
+    trace["arrival_s"] = inputs.poisson_arrivals(count, rate, seed + 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, st = serve.run(trace, budget, streams=streams)
+    wall = time.perf_counter() - t0
+    summ = serve.summarize(trace, res, st)
+    # the same trace again with every request's output digested on the device
+    res_v, st_v = serve.run(trace, budget, streams=streams, verify=True)
+    ok = bool(np.all(res_v["flags"] == 0) and np.array_equal(res_v["count"], trace["n"]))
+    out = {
+        "metric": METRIC, "value": round(summ["gkeys_per_s"], 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": round(st["makespan_s"] * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "serve", "requests": count, "sizes": "log-uniform in [2^10, 2^24]",
+                   "range": "next power of two >= 4n", "arrivals": f"Poisson, {rate:.1f} requests/s",
+                   "budget_bytes": budget, "streams": streams, "total_keys": int(trace["n"].sum())},
+        "latency_ms": {"p50": round(summ["p50_ms"], 4), "p99": round(summ["p99_ms"], 4),
+                       "mean_queue": round(summ["mean_queue_ms"], 4),
+                       "mean_launch_to_keys_ready": round(summ["mean_launch_to_keys_ready_ms"], 4),
+                       "keys_ready_share": round(summ["keys_ready_share_of_latency"], 4)},
+        "launches": summ["launches"], "max_inflight_requests": summ["max_inflight_requests"],
+        "peak_bytes": summ["peak_bytes"], "host_wall_s": round(wall, 3),
+        "calibration": {"burst_gkeys_per_s": round(t_burst / 1e9, 3),
+                        "one_request_per_launch_gkeys_per_s": round(t_one / 1e9, 3),
+                        "burst_over_one_by_one": round(t_burst / t_one, 3), "requests": 512},
+        "verify_run": {"all_counts_and_flags_ok": ok, "gkeys_per_s": round(st_v["keys"] / st_v["makespan_s"] / 1e9, 3)},
+    }
+    if not args.no_cpu_baseline:
+        gk, checked, keys_done, t_sort, bad = serve_cpu_baseline(trace, res_v)
+        out["cpu_baseline"] = {"value": round(gk, 4), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{checked} requests of the trace ({keys_done} keys) sorted by the oracle, "
+                                         f"{t_sort:.2f} s; inputs regenerated on the host"}
+        out["oracle_digests_match"] = not bad
+        if bad:
+            out["oracle_mismatch_requests"] = bad[:20]
+    return out
+
+
 def copy_calibration(args):
     """A plain device copy of known size (1 GiB read + 1 GiB written per
     launch), for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters and as
@@ -359,7 +450,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="plain-uniform", choices=sorted(PLAIN) + ["batch", "copy-calibration"])
+    ap.add_argument("--workload", default="plain-uniform", choices=sorted(PLAIN) + ["batch", "serve", "copy-calibration"])
+    ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--pool", type=int, default=0, help="input buffers to rotate through (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", default="", help="slice_bits,tile_log2,emit_path (0 = library choice)")
@@ -374,6 +467,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         result = bench_batch(args)
+    elif args.workload == "serve":
+        result = bench_serve(args)
     elif args.workload == "copy-calibration":
         result = copy_calibration(args)
     else:

@@ -232,6 +232,81 @@ int bitsort_tuning_load(const char *path, int *entries);
 int bitsort_tuning_clear(void);
 
 /*
+ * Serving loop: continuous batching of sort requests under a device-memory
+ * budget.  Request i names a synthetic input -- n keys pi(0 .. n-1) of the
+ * seeded keyed permutation of [0, 2^range_bits), the bitsort_generate_u32
+ * generator -- and an arrival time.  The loop admits requests in arrival
+ * order as launch slots and memory free up, materialises their keys on the
+ * device, and sorts them: requests with range_bits <= plain_range_bits
+ * together in one segmented launch (at most max_batch_requests requests and,
+ * unless one request alone exceeds it, max_batch_keys keys), wider ones one
+ * by one through the plain path, whose partition pass reads the keys once
+ * however wide the range (the segmented kernel reads a segment once per
+ * 2^20-bit slice of its range); up to
+ * `streams` launches are in flight at once, each on its own stream.  The
+ * memory of a launch (keys, output, workspace) is one region of an arena of
+ * budget_bytes, held until the launch finishes.  Requests that arrive while
+ * others run are admitted as soon as a slot and memory are free.  A request
+ * that cannot fit the budget on its own is rejected.  The call blocks until
+ * every request is done (real time: arrivals are released at arrival_s
+ * seconds after the start; simulate = 1 runs the same scheduler on a virtual
+ * clock with no GPU, the device serving launches one after another in
+ * sim_overhead_s + keys / sim_keys_per_s).  With verify = 1 each request's
+ * result carries the digest of its sorted output (see bitsort_digest_u32), so
+ * it can be compared with the same request sorted alone.  Times are seconds
+ * from the start of the call; GPU-side times come from HIP events.
+ */
+#define BITSORT_REQ_REJECTED 8u  /* result flag: larger than the whole budget */
+#define BITSORT_REQ_INVALID 16u  /* result flag: range_bits > 32 or n > 2^range_bits */
+
+typedef struct bitsort_request {
+    uint64_t n;
+    uint32_t range_bits;
+    uint32_t _pad;
+    uint64_t seed;
+    double arrival_s;
+} bitsort_request_t;
+
+typedef struct bitsort_request_result {
+    double launch_s;  /* left the queue: memory reserved and its launch enqueued */
+    double ready_s;   /* its keys were materialised on the GPU (the sort starts after this) */
+    double done_s;    /* its launch finished on the GPU */
+    uint64_t digest;  /* digest of its sorted output (verify = 1), else 0 */
+    uint64_t count;   /* keys written */
+    uint32_t flags;   /* BITSORT_STATUS_* | BITSORT_REQ_* */
+    uint32_t batch;   /* index of the launch that carried it */
+} bitsort_request_result_t;
+
+typedef struct bitsort_serve_config {
+    uint64_t budget_bytes;
+    uint32_t streams;            /* 1 .. 16 */
+    uint32_t max_batch_requests; /* >= 1 */
+    uint64_t max_batch_keys;     /* >= 1 */
+    uint32_t plain_range_bits;   /* wider requests run alone on the plain path; 0: 20, at most 24 */
+    uint32_t verify;
+    uint32_t simulate;
+    uint32_t _pad;
+    double sim_overhead_s;
+    double sim_keys_per_s;
+} bitsort_serve_config_t;
+
+typedef struct bitsort_serve_stats {
+    double makespan_s;              /* first arrival to last completion */
+    uint64_t keys;                  /* keys written in all */
+    uint32_t launches;
+    uint32_t max_inflight_requests;
+    uint64_t peak_bytes;            /* most arena bytes held at once */
+} bitsort_serve_stats_t;
+
+int bitsort_serve_run(const bitsort_request_t *requests, uint32_t count, const bitsort_serve_config_t *config,
+                      bitsort_request_result_t *results, bitsort_serve_stats_t *stats);
+
+/* Order-dependent digest of n uint32 values on the device:
+ * sum over i of SplitMix64_finalizer((i << 32) ^ data[i] + 0x9E3779B97F4A7C15)
+ * modulo 2^64.  Synchronises `stream`; *digest is a host pointer. */
+int bitsort_digest_u32(const uint32_t *data, uint64_t n, uint64_t *digest, bitsort_stream_t stream);
+
+/*
  * Kernel timing for benchmarks.  While enabled, every kernel the library
  * launches is bracketed by two HIP events recorded on the launch's own
  * stream.  bitsort_profile_read() waits for those events and returns, per

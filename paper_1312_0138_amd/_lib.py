@@ -20,6 +20,8 @@ BITSORT_ERR_HIP = 4
 STATUS_OUT_OF_RANGE = 1
 STATUS_DUPLICATE = 2
 STATUS_BAD_SEGMENT = 4
+REQ_REJECTED = 8
+REQ_INVALID = 16
 
 BATCH_MAX_RANGE_BITS = 24
 
@@ -73,6 +75,8 @@ _SIGS = {
     "bitsort_tuning_save": (_c.c_int, [_c.c_char_p]),
     "bitsort_tuning_load": (_c.c_int, [_c.c_char_p, _c.POINTER(_c.c_int)]),
     "bitsort_tuning_clear": (_c.c_int, []),
+    "bitsort_serve_run": (_c.c_int, [_vp, _u32, _vp, _vp, _vp]),
+    "bitsort_digest_u32": (_c.c_int, [_vp, _u64, _c.POINTER(_u64), _vp]),
     "bitsort_profile_enable": (_c.c_int, [_c.c_int]),
     "bitsort_profile_reset": (_c.c_int, []),
     "bitsort_profile_read": (_c.c_int, [_c.POINTER(ProfileEntry), _c.c_int, _c.POINTER(_c.c_int)]),
@@ -256,3 +260,15 @@ def bitsort_tuning_load(path: str):
 
 def bitsort_tuning_clear() -> int:
     return lib().bitsort_tuning_clear()
+
+
+def bitsort_serve_run(requests: int, count: int, config: int, results: int, stats: int) -> int:
+    """Pointers to arrays laid out as bitsort_request_t / _config_t /
+    _request_result_t / _serve_stats_t (see serve.py for the dtypes)."""
+    return lib().bitsort_serve_run(requests, count, config, results, stats)
+
+
+def bitsort_digest_u32(data: int, n: int, stream: int):
+    d = _u64()
+    rc = lib().bitsort_digest_u32(data, n, ctypes.byref(d), stream)
+    return rc, d.value

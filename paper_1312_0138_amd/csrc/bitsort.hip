@@ -47,9 +47,14 @@
 #include <mutex>
 #include <utility>
 #include <vector>
+#include <chrono>
+#include <cmath>
 #include <cstdio>
+#include <deque>
 #include <functional>
+#include <limits>
 #include <string>
+#include <thread>
 
 #include "bitsort.h"
 #include "bitsort_device.h"
@@ -1192,6 +1197,8 @@ void splitmix_keys(uint64_t seed, uint32_t k[4]) {
   }
 }
 
+#include "serve.inc"
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1649,6 +1656,60 @@ int bitsort_tuning_clear(void) {
   g_batch_tuned = BatchTuning{};
   return BITSORT_OK;
 }
+
+int bitsort_serve_run(const bitsort_request_t* requests, uint32_t count, const bitsort_serve_config_t* config,
+                      bitsort_request_result_t* results, bitsort_serve_stats_t* stats) {
+  if (config == nullptr || (count > 0 && (requests == nullptr || results == nullptr))) return BITSORT_ERR_INVALID_ARG;
+  const bitsort_serve_config_t& c = *config;
+  if (c.streams < 1 || c.streams > 16 || c.max_batch_requests < 1 || c.max_batch_keys < 1 || c.budget_bytes == 0)
+    return BITSORT_ERR_INVALID_ARG;
+  if (c.simulate && !(c.sim_keys_per_s > 0.0 && c.sim_overhead_s >= 0.0)) return BITSORT_ERR_INVALID_ARG;
+  if (c.max_batch_requests > BITSORT_BATCH_MAX_SEGMENTS) return BITSORT_ERR_INVALID_ARG;
+  serve::Arena arena;
+  arena.init(c.budget_bytes);
+  if (c.simulate) {
+    serve::SimExecutor ex(c.sim_overhead_s, c.sim_keys_per_s);
+    return serve::schedule(ex, arena, requests, count, c, results, stats, true);
+  }
+  int rc = init_kernels();
+  if (rc != BITSORT_OK) return rc;
+  void* base = nullptr;
+  if (hipMalloc(&base, c.budget_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return BITSORT_ERR_NO_MEMORY;
+  }
+  {
+    serve::HipExecutor ex;
+    rc = ex.init(static_cast<char*>(base), c.streams, c.verify != 0, c.max_batch_requests);
+    if (rc == BITSORT_OK) rc = serve::schedule(ex, arena, requests, count, c, results, stats, false);
+  }
+  (void)hipDeviceSynchronize();
+  (void)hipFree(base);
+  return rc;
+}
+
+int bitsort_digest_u32(const uint32_t* data, uint64_t n, uint64_t* digest, bitsort_stream_t stream) {
+  if (digest == nullptr || (n > 0 && data == nullptr)) return BITSORT_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint64_t* dev = nullptr;
+  if (hipMalloc(&dev, 64) != hipSuccess) return BITSORT_ERR_NO_MEMORY;
+  const uint64_t hoff[2] = {0, n};
+  int rc = BITSORT_OK;
+  if (hipMemcpyAsync(dev + 1, hoff, 16, hipMemcpyHostToDevice, s) != hipSuccess) rc = BITSORT_ERR_HIP;
+  if (rc == BITSORT_OK) {
+    hipLaunchKernelGGL(serve::k_fill_u64, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned long long*>(dev), 1u);
+    if (n > 0)
+      hipLaunchKernelGGL(serve::k_digest, dim3(static_cast<uint32_t>((n + serve::kDigestChunk - 1) / serve::kDigestChunk)),
+                         dim3(256), 0, s, data, dev + 1, 1u, n, reinterpret_cast<unsigned long long*>(dev));
+    rc = launch_status();
+  }
+  if (rc == BITSORT_OK && (hipMemcpyAsync(digest, dev, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                           hipStreamSynchronize(s) != hipSuccess))
+    rc = BITSORT_ERR_HIP;
+  (void)hipFree(dev);
+  return rc;
+}
+
 
 int bitsort_profile_enable(int on) {
   g_prof_on.store(on != 0);
