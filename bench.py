@@ -50,10 +50,18 @@ PLAIN = {
 }
 
 
-def source_digest() -> str:
+KERNEL_SOURCES = {
+    "plain": ["bitsort_device.h", "plain_kernels.inc"],
+    "batch": ["bitsort_device.h", "plain_kernels.inc", "batch_kernels.inc"],
+}
+
+
+def source_digest(which: str = "plain") -> str:
+    """Digest of the device sources a workload's kernels are built from: a
+    stored counter reading is used only while it matches."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1312_0138_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in KERNEL_SOURCES[which]:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -404,6 +412,7 @@ def bench_serve(args):
                        "mean_launch_to_keys_ready": round(summ["mean_launch_to_keys_ready_ms"], 4),
                        "keys_ready_share": round(summ["keys_ready_share_of_latency"], 4)},
         "launches": summ["launches"], "max_inflight_requests": summ["max_inflight_requests"],
+        "requests_per_launch": summ["requests_per_launch"],
         "peak_bytes": summ["peak_bytes"], "host_wall_s": round(wall, 3),
         "calibration": {"burst_gkeys_per_s": round(t_burst / 1e9, 3),
                         "one_request_per_launch_gkeys_per_s": round(t_one / 1e9, 3),

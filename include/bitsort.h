@@ -140,7 +140,8 @@ int bitsort_batch_status(bitsort_stream_t stream, bitsort_status_t *status, uint
 /*
  * Device-side input generator (the synthetic workloads): out[i] = pi(first + i)
  * for i < count, where pi is the seeded keyed permutation of [0, 2^range_bits)
- * (4-round Feistel network with cycle walking; round keys from SplitMix64).
+ * (4-round alternating Feistel network over halves of ceil(range_bits/2) and
+ * floor(range_bits/2) bits; round keys from SplitMix64).
  * Gives distinct keys in pseudo-random order.  first + count <= 2^range_bits.
  */
 int bitsort_generate_u32(uint32_t *out, uint64_t first, uint64_t count, uint32_t range_bits,
@@ -245,7 +246,9 @@ int bitsort_tuning_clear(void);
  * 2^20-bit slice of its range); up to
  * `streams` launches are in flight at once, each on its own stream.  The
  * memory of a launch (keys, output, workspace) is one region of an arena of
- * budget_bytes, held until the launch finishes.  Requests that arrive while
+ * budget_bytes, held until the launch finishes.  The arena is the caller's
+ * device memory at `arena` (256-byte aligned, not touched by anything else
+ * during the call) or, when that is NULL, allocated and freed by the call.  Requests that arrive while
  * others run are admitted as soon as a slot and memory are free.  A request
  * that cannot fit the budget on its own is rejected.  The call blocks until
  * every request is done (real time: arrivals are released at arrival_s
@@ -278,11 +281,12 @@ typedef struct bitsort_request_result {
 } bitsort_request_result_t;
 
 typedef struct bitsort_serve_config {
+    void *arena;                 /* device memory of budget_bytes for the arena, or NULL: allocated per call */
     uint64_t budget_bytes;
     uint32_t streams;            /* 1 .. 16 */
     uint32_t max_batch_requests; /* >= 1 */
     uint64_t max_batch_keys;     /* >= 1 */
-    uint32_t plain_range_bits;   /* wider requests run alone on the plain path; 0: 20, at most 24 */
+    uint32_t plain_range_bits;   /* wider requests run alone on the plain path; 0: BITSORT_BATCH_MAX_RANGE_BITS */
     uint32_t verify;
     uint32_t simulate;
     uint32_t _pad;

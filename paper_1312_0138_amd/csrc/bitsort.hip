@@ -1,4 +1,4 @@
-// bitsort.hip -- gfx950 (MI355X) kernels and C ABI of the bitmap sort.
+// bitsort.hip -- host side and C ABI of the gfx950 (MI355X) bitmap sort.
 //
 // The operation is the one of Yordzhev, arXiv:1312.0138: sort an integer
 // array ascending (Section IV, Theorem 1), done here the bit-vector way from
@@ -11,10 +11,10 @@
 // MI355X design.  Global atomics on this part resolve at about 27 G ops/s no
 // matter the footprint, so marking n random keys straight into an HBM
 // bit-vector costs n atomics at that rate -- tens of times the streaming
-// time of the keys.  LDS atomics run at about 2-3 T ops/s.  So the bit-vector
-// never lives in HBM: it is cut into slices of 2^sb bits that fit in one
-// workgroup's LDS (up to 2^20 bits = 128 KiB of the 160 KiB), and the keys
-// are routed to their slice first:
+// time of the keys.  LDS atomics run at about 2-3 T ops/s.  So keys are never
+// marked in HBM: the bit-vector is cut into slices of 2^sb bits that fit in
+// one workgroup's LDS (up to 2^20 bits = 128 KiB of the 160 KiB), and the
+// keys are routed to their slice first (plain_kernels.inc):
 //
 //   k_partition  one workgroup per tile of T keys: counts keys per slice
 //                (LDS histogram), exclusive-scans the counts, groups the tile
@@ -22,21 +22,29 @@
 //                area at the tile's own offset, plus the tile's per-slice
 //                start offsets (a row of the tile table).
 //   k_slice      one workgroup per slice: clears its LDS slice, reads that
-//                slice's segment from every tile (64 keys per wave load, 8
-//                loads in flight per wave) and ORs the bits in with ds_or;
-//                then counts ones per word and prefix-sums them with ballot /
-//                mbcnt, and writes each word's set-bit positions (ctz, clear
-//                lowest bit) through an LDS staging buffer so that stores to
-//                `out` are contiguous.  The slice's output base -- the
-//                device-wide exclusive prefix over slices -- is the sum over
-//                tiles of the tile-local starts, read from the table with no
-//                extra pass.
+//                slice's part of every tile (64 keys per wave load, many
+//                loads in flight per wave) and ORs the bits in with ds_or.
+//                For sparse keys (R/8 > 2n) it then counts ones per word,
+//                prefix-sums them with ballot / mbcnt and writes each word's
+//                set-bit positions (ctz, clear lowest bit) through LDS so
+//                that stores to `out` are contiguous; the slice's output
+//                base -- the exclusive prefix over slices -- is the sum over
+//                tiles of the tile-local starts.  When the bit-vector is
+//                small next to the keys (R/8 <= 2n) it instead writes the
+//                slice's words to an HBM bit-vector plus per-chunk prefix
+//                counts, and
+//   k_emit       scans that bit-vector in 1024-word chunks and writes the
+//                keys: many small workgroups share the emission evenly
+//                instead of one workgroup per slice.
+//   k_finish     one workgroup: totals, status flags, and (only when keys
+//                repeat) compaction of the slices' outputs.
 //   k_direct     a single workgroup for key ranges that fit one slice and
 //                small n: mark, scan and emit without the partition.
 //
-// HBM traffic of the two-kernel path: 4n (keys) + 4n + 4n (staging write and
-// read) + 4n (out) bytes plus the tile table; the bit-vector itself costs only
-// LDS bandwidth.
+// HBM traffic of the path: 4n (keys) + 4n + 4n (staging write and read) +
+// 4n (out) bytes plus the tile table; the bit-vector adds 2 x R/8 only on the
+// k_emit path.  Other files: batch_kernels.inc (segmented batch launch),
+// generate.inc (input generator), serve.inc (serving loop).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,745 +71,13 @@ using namespace bitsort_dev;
 
 namespace {
 
-constexpr uint32_t kLdsBytes = 160 * 1024;    // LDS per workgroup on gfx950
-constexpr uint32_t kMaxSliceBits = 20;        // 2^20 bits = 128 KiB of LDS
-constexpr uint32_t kMinSliceBits = 10;
-constexpr uint32_t kMaxBucketsLog2 = 12;      // partition fan-out <= 4096
-constexpr uint32_t kSliceBlock = 1024;
-constexpr uint32_t kSliceUnroll = 32;
-constexpr uint32_t kDirectBlock = 1024;
-constexpr uint64_t kDirectMaxN = 8192;        // single-workgroup path below this
-constexpr uint32_t kHeaderBytes = 256;        // status + scratch header in LDS / workspace
-constexpr uint32_t kStageMax = 8192;
-constexpr uint32_t kBatchSliceBits = 20;
-constexpr uint32_t kChunkWords = 1024;        // words per k_emit workgroup
-constexpr uint32_t kEmitBlock = 256;
-constexpr uint32_t kEmitWindow = 1024;        // LDS window per wave in k_emit (words)
-
-enum Mode : int { kEmit = 0, kDumpBitmap = 1, kDumpPrefix = 2, kToBitVector = 3 };
-
-__host__ __device__ constexpr uint32_t round_up4(uint32_t x) { return (x + 3u) & ~3u; }
+#include "plain_kernels.inc"
 
 // ---------------------------------------------------------------------------
-// Scan and emit one LDS slice (Example 6 per word, then Example 1 per bit).
-//
-// slice[0 .. slice_words) holds the marked bits of keys key_base + 32*w + b.
-// Count pass: wave v owns the word range [v*per, (v+1)*per) and sums the
-// ones in it; one barrier turns the per-wave sums into each wave's output
-// offset.  Emit pass, with no further block barrier: the wave walks its range
-// 64 words at a time (lane l <-> word w0 + l), forms the exclusive prefix p of
-// the per-word counts with ballot bit planes, and writes word w's keys
-// key_base + 32w + ctz(x) (clearing the lowest set bit each time) to
-// out[D + p ...].  Three shapes:
-//   - no word has more than one key: each key goes straight to its rank
-//     among the nonzero lanes (one store for the whole group);
-//   - all 64 words full: 2048 consecutive keys, stored as a sequence;
-//   - otherwise the keys are staged in the wave's own LDS window at their
-//     prefix positions (offset by the destination's 16-byte phase) and copied
-//     out with 16-byte stores, in as many windows as the group needs.
-// Returns the number of set bits (uniform).  Every thread of the block calls
-// it.  mode != kEmit writes the bit-vector or the per-word prefix instead.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-  for (uint32_t d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-  return v;
-}
-
-// Copy ws[shift .. shift + m) to dst[0 .. m), where dst + e is 16-byte
-// aligned exactly when (shift + e) % 4 == 0.
-__device__ __forceinline__ void wave_copy_out(const uint32_t* ws, uint32_t shift, uint32_t* dst, uint32_t m) {
-  const uint32_t lane = lane_id();
-  uint32_t h = (4u - shift) & 3u;
-  if (h > m) h = m;
-  if (lane < h) dst[lane] = ws[shift + lane];
-  const uint32_t q = (m - h) >> 2;
-  const uint4* src4 = reinterpret_cast<const uint4*>(ws + shift + h);
-  uint4* dst4 = reinterpret_cast<uint4*>(dst + h);
-  for (uint32_t v = lane; v < q; v += kWave) dst4[v] = src4[v];
-  const uint32_t t0 = h + (q << 2);
-  if (t0 + lane < m) dst[t0 + lane] = ws[shift + t0 + lane];
-}
-
-template <int BLOCK>
-__device__ uint64_t scan_emit(const uint32_t* slice, uint32_t slice_words, uint32_t key_base,
-                              uint32_t* stage, uint32_t stage_cap, uint32_t* scratch,
-                              uint32_t* __restrict__ out, uint64_t out_base, int mode,
-                              uint32_t* dbg_bitmap, uint64_t* dbg_prefix, uint64_t dbg_word0) {
-  constexpr uint32_t kWaves = BLOCK / kWave;
-  const uint32_t lane = threadIdx.x & (kWave - 1);
-  const uint32_t wave = threadIdx.x / kWave;
-  const uint32_t per = (slice_words + kWaves - 1) / kWaves;
-  const uint32_t w_lo = min(wave * per, slice_words), w_hi = min(w_lo + per, slice_words);
-
-  uint32_t cnt = 0;
-  for (uint32_t w = w_lo + lane; w < w_hi; w += kWave) cnt += static_cast<uint32_t>(__popc(slice[w]));
-  cnt = wave_sum_u32(cnt);
-  if (lane == 0) scratch[wave] = cnt;
-  __syncthreads();
-  uint64_t wbase = 0, total = 0;
-#pragma unroll
-  for (uint32_t i = 0; i < kWaves; ++i) {
-    const uint32_t v = scratch[i];
-    wbase += (i < wave) ? v : 0u;
-    total += v;
-  }
-  total = uniform(total);
-  wbase = uniform(wbase);
-  __syncthreads();  // scratch is reused by the caller
-
-  const uint32_t wsw = (stage_cap / kWaves) & ~3u;  // this wave's LDS window, 16-byte aligned
-  uint32_t* ws = stage + wave * wsw;
-  const uint32_t win = wsw - 4u;
-  uint64_t D = out_base + wbase;
-  for (uint32_t w0 = w_lo; w0 < w_hi; w0 += kWave) {
-    const uint32_t w = w0 + lane;
-    const uint32_t x = (w < w_hi) ? slice[w] : 0u;
-    const uint32_t c = static_cast<uint32_t>(__popc(x));
-    if (mode == kEmit) {
-      const uint64_t nz = __ballot(c != 0u);
-      if (nz == 0) continue;
-      if (__ballot(c > 1u) == 0) {
-        if (c != 0u) out[D + count_below(nz)] = key_base + (w << 5) + static_cast<uint32_t>(__builtin_ctz(x));
-        D += static_cast<uint32_t>(__popcll(nz));
-        continue;
-      }
-      if (w0 + kWave <= w_hi && __ballot(x != 0xFFFFFFFFu) == 0) {
-        const uint32_t kb0 = key_base + (w0 << 5);
-#pragma unroll 8
-        for (uint32_t j = 0; j < 32; ++j) out[D + j * kWave + lane] = kb0 + j * kWave + lane;
-        D += 32u * kWave;
-        continue;
-      }
-    }
-    uint32_t tot;
-    const uint32_t p = wave_prefix_small(c, &tot);
-    tot = uniform(tot);
-    if (mode == kDumpBitmap) {
-      if (w < w_hi) dbg_bitmap[dbg_word0 + w] = x;
-    } else if (mode == kDumpPrefix) {
-      if (w < w_hi) dbg_prefix[dbg_word0 + w] = D + p;
-    } else {
-      for (uint32_t lo = 0; lo < tot; lo += win) {
-        uint32_t* dst = out + D + lo;
-        const uint32_t shift = static_cast<uint32_t>((reinterpret_cast<uintptr_t>(dst) >> 2) & 3u);
-        if (c != 0u && p < lo + win && p + c > lo) {
-          uint32_t y = x, pos = p;
-          while (pos < lo) {  // drop the bits that belong to earlier windows
-            y &= y - 1u;
-            ++pos;
-          }
-          const uint32_t kb = key_base + (w << 5);
-          while (y != 0u && pos < lo + win) {
-            ws[shift + pos - lo] = kb + static_cast<uint32_t>(__builtin_ctz(y));
-            y &= y - 1u;
-            ++pos;
-          }
-        }
-        wave_sync();
-        wave_copy_out(ws, shift, dst, min(win, tot - lo));
-        wave_sync();
-      }
-    }
-    D += tot;
-  }
-  return total;
-}
-
-// One workgroup moves every slice's output left so that the slices' keys are
-// contiguous (only after a duplicate key made some slice write fewer keys than
-// its share).  info[3b] = where slice b wrote, info[3b+1] = how many.
-template <int BLOCK>
-__device__ void compact_slices(uint32_t* out, const uint64_t* info, uint32_t nb) {
-  uint64_t dst = 0;
-  for (uint32_t b = 0; b < nb; ++b) {
-    const uint64_t src = uniform(info[3 * b]);
-    const uint64_t cnt = uniform(info[3 * b + 1]);
-    if (src != dst) {
-      for (uint64_t i0 = 0; i0 < cnt; i0 += BLOCK) {
-        const uint64_t i = i0 + threadIdx.x;
-        uint32_t v = 0;
-        if (i < cnt) v = out[src + i];
-        __syncthreads();  // dst <= src: read this chunk before any thread overwrites it
-        if (i < cnt) out[dst + i] = v;
-        __syncthreads();
-      }
-    }
-    dst += cnt;
-  }
-}
+#include "generate.inc"
 
 // ---------------------------------------------------------------------------
-// Partition: route each key of a tile to its slice (mark, first half).
-//
-// LDS: [scratch 32 words][hist nb words, padded to 4][tile keys T words].
-template <int BLOCK, int ITEMS>
-__global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t* __restrict__ keys, uint64_t n,
-                                                     uint64_t range, uint32_t sb, uint32_t nb,
-                                                     uint32_t* __restrict__ staging,
-                                                     uint32_t* __restrict__ table, int vec_ok) {
-  static_assert(ITEMS % 4 == 0, "ITEMS must be a multiple of 4");
-  constexpr uint32_t T = BLOCK * ITEMS;
-  extern __shared__ __align__(16) uint32_t lds[];
-  uint32_t* scratch = lds;
-  uint32_t* hist = lds + 32;
-  uint32_t* tk = lds + 32 + round_up4(nb);
-  const uint32_t tid = threadIdx.x;
-  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * T;
-  const uint32_t cnt = static_cast<uint32_t>(min(static_cast<uint64_t>(T), n - base));
-  for (uint32_t i = tid; i < nb; i += BLOCK) hist[i] = 0u;
-  __syncthreads();
-
-  uint32_t k[ITEMS], r[ITEMS];
-  if (vec_ok && cnt == T) {
-    const uint4* src = reinterpret_cast<const uint4*>(keys + base);
-#pragma unroll
-    for (int j = 0; j < ITEMS / 4; ++j) {
-      const uint4 q = src[tid + j * BLOCK];
-      k[4 * j] = q.x;
-      k[4 * j + 1] = q.y;
-      k[4 * j + 2] = q.z;
-      k[4 * j + 3] = q.w;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < ITEMS / 4; ++j)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const uint32_t idx = (tid + j * BLOCK) * 4u + c;
-        k[4 * j + c] = idx < cnt ? keys[base + idx] : 0u;
-      }
-  }
-  // Rank of each key inside its slice's group (order inside a group is
-  // irrelevant: the slice ORs them).  Keys >= range are dropped here.
-#pragma unroll
-  for (int j = 0; j < ITEMS / 4; ++j)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int i = 4 * j + c;
-      const uint32_t idx = (tid + j * BLOCK) * 4u + c;
-      const bool valid = idx < cnt && static_cast<uint64_t>(k[i]) < range;
-      r[i] = valid ? atomicAdd(&hist[k[i] >> sb], 1u) : 0xFFFFFFFFu;
-    }
-  __syncthreads();
-
-  // Exclusive scan of the nb counts -> group starts; also the table row.
-  const uint32_t per = (nb + BLOCK - 1) / BLOCK;
-  const uint32_t lo = tid * per;
-  uint32_t s = 0;
-  for (uint32_t e = 0; e < per; ++e)
-    if (lo + e < nb) s += hist[lo + e];
-  uint32_t tot;
-  const uint32_t pre = block_excl_scan<BLOCK>(s, scratch, &tot);
-  uint32_t* row = table + static_cast<uint64_t>(blockIdx.x) * (nb + 1u);
-  uint32_t run = pre;
-  for (uint32_t e = 0; e < per; ++e)
-    if (lo + e < nb) {
-      const uint32_t h = hist[lo + e];
-      hist[lo + e] = run;
-      row[lo + e] = run;
-      run += h;
-    }
-  if (tid == 0) row[nb] = tot;
-  __syncthreads();
-
-#pragma unroll
-  for (int i = 0; i < ITEMS; ++i)
-    if (r[i] != 0xFFFFFFFFu) tk[hist[k[i] >> sb] + r[i]] = k[i];
-  __syncthreads();
-
-  uint32_t* dst = staging + base;
-  const uint32_t n4 = tot >> 2;
-  const uint4* tk4 = reinterpret_cast<const uint4*>(tk);
-  uint4* dst4 = reinterpret_cast<uint4*>(dst);
-  for (uint32_t i = tid; i < n4; i += BLOCK) dst4[i] = tk4[i];
-  for (uint32_t i = (n4 << 2) + tid; i < tot; i += BLOCK) dst[i] = tk[i];
-}
-
-// ---------------------------------------------------------------------------
-// Slice: mark (second half), scan and emit one slice.
-//
-// Workgroups are handed out round-robin over the eight XCDs (blockIdx % 8),
-// so blockIdx is mapped to slices such that each XCD takes a contiguous run of
-// slices: the segments of neighbouring slices share cache lines at their
-// boundaries, and these are then read through the same L2.
-//
-// LDS: [scratch64 16 u64][scratch 32 words][slice 2^sb bits][stage].
-template <int BLOCK, int UNROLL>
-__device__ __forceinline__ void load_units(uint32_t u0, uint32_t utot, uint32_t upre, uint32_t s, uint32_t e,
-                                           uint32_t lane, uint32_t t0, uint32_t tile_keys,
-                                           const uint32_t* __restrict__ staging, uint32_t* kk, bool* vv) {
-#pragma unroll
-  for (int q = 0; q < UNROLL; ++q) {
-    const uint32_t u = u0 + q;
-    vv[q] = false;
-    kk[q] = 0u;
-    if (u < utot) {
-      // Owner of unit u: the last lane whose unit prefix is <= u.
-      const uint64_t m = __ballot(upre <= u);
-      const uint32_t j = static_cast<uint32_t>(__popcll(m)) - 1u;
-      const uint32_t sj = __builtin_amdgcn_readlane(s, j);
-      const uint32_t ej = __builtin_amdgcn_readlane(e, j);
-      const uint32_t pj = __builtin_amdgcn_readlane(upre, j);
-      const uint32_t idx = sj + (u - pj) * kWave + lane;
-      if (idx < ej) {
-        kk[q] = staging[static_cast<uint64_t>(t0 + j) * tile_keys + idx];
-        vv[q] = true;
-      }
-    }
-  }
-}
-
-template <int BLOCK, int UNROLL>
-__global__ __launch_bounds__(BLOCK) void k_slice(const uint32_t* __restrict__ staging,
-                                                 const uint32_t* __restrict__ table, uint32_t nt,
-                                                 uint32_t tile_keys, uint32_t sb, uint32_t nb,
-                                                 uint32_t stage_cap, uint32_t* __restrict__ out,
-                                                 uint64_t* __restrict__ info, int mode,
-                                                 uint32_t* dbg_bitmap, uint64_t* dbg_prefix,
-                                                 uint32_t* __restrict__ bitvec, uint64_t* __restrict__ chunk_base) {
-  constexpr uint32_t kWaves = BLOCK / kWave;
-  extern __shared__ __align__(16) uint32_t lds[];
-  uint64_t* scratch64 = reinterpret_cast<uint64_t*>(lds);
-  uint32_t* scratch = lds + 32;
-  uint32_t* slice = lds + 64;
-  const uint32_t slice_words = (sb >= 5) ? (1u << (sb - 5)) : 1u;
-  uint32_t* stage = slice + round_up4(slice_words);
-  const uint32_t tid = threadIdx.x;
-  const uint32_t lane = tid & (kWave - 1);
-  const uint32_t wave = tid / kWave;
-  const uint32_t per8 = (nb + 7u) / 8u;
-  const uint32_t b = (blockIdx.x % 8u) * per8 + blockIdx.x / 8u;
-  if (b >= nb) return;  // padding block of the 8-way mapping
-
-  for (uint32_t i = tid; i < slice_words; i += BLOCK) slice[i] = 0u;
-  __syncthreads();
-
-  // Mark: the wave takes 64 tiles at a time (lane l <-> tile t0 + l), turns
-  // their segments for slice b into 64-key units, and each unit is one
-  // coalesced load of 64 keys followed by 64 ds_or (Table I's OR).
-  const uint32_t smask = (1u << sb) - 1u;
-  uint64_t base_acc = 0, cnt_acc = 0;
-  for (uint32_t t0 = wave * kWave; t0 < nt; t0 += kWaves * kWave) {
-    const uint32_t t = t0 + lane;
-    uint32_t s = 0, e = 0;
-    if (t < nt) {
-      const uint32_t* row = table + static_cast<uint64_t>(t) * (nb + 1u);
-      s = row[b];
-      e = row[b + 1u];
-    }
-    base_acc += s;
-    cnt_acc += e - s;
-    const uint32_t units = (e - s + kWave - 1u) / kWave;
-    const uint32_t inc = wave_incl_scan(units);
-    const uint32_t upre = inc - units;
-    const uint32_t utot = uniform(static_cast<uint32_t>(__shfl(inc, kWave - 1, kWave)));
-    for (uint32_t u0 = 0; u0 < utot; u0 += UNROLL) {
-      uint32_t kk[UNROLL];
-      bool vv[UNROLL];
-      load_units<BLOCK, UNROLL>(u0, utot, upre, s, e, lane, t0, tile_keys, staging, kk, vv);
-#pragma unroll
-      for (int q = 0; q < UNROLL; ++q)
-        if (vv[q]) {
-          const uint32_t l = kk[q] & smask;
-          atomicOr(&slice[l >> 5], 1u << (l & 31u));
-        }
-    }
-  }
-  const uint64_t base_b = block_sum_u64<BLOCK>(base_acc, scratch64);  // also orders the marks before the scan
-  const uint64_t cnt_b = block_sum_u64<BLOCK>(cnt_acc, scratch64);
-
-  if (mode == kToBitVector) {
-    // Scan step only: the slice goes to the bit-vector in HBM, and every
-    // kChunkWords-word chunk gets its exclusive prefix of set bits over the
-    // whole bit-vector (the slice's base plus the chunks before it).
-    const uint32_t nchunk = slice_words / kChunkWords;
-    for (uint32_t c = wave; c < nchunk; c += kWaves) {
-      uint32_t cnt = 0;
-      for (uint32_t w = c * kChunkWords + lane; w < (c + 1) * kChunkWords; w += kWave)
-        cnt += static_cast<uint32_t>(__popc(slice[w]));
-      cnt = wave_sum_u32(cnt);
-      if (lane == 0) stage[c] = cnt;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      uint64_t run = base_b;  // nchunk <= 32: one wave scans the chunk counts
-      for (uint32_t c0 = 0; c0 < nchunk; c0 += kWave) {
-        const uint32_t c = c0 + lane;
-        const uint32_t v = c < nchunk ? stage[c] : 0u;
-        const uint32_t inc = wave_incl_scan(v);
-        if (c < nchunk) chunk_base[static_cast<uint64_t>(b) * nchunk + c] = run + inc - v;
-        run += uniform(static_cast<uint32_t>(__shfl(inc, kWave - 1, kWave)));
-      }
-      if (lane == 0) {
-        info[3 * b] = base_b;
-        info[3 * b + 1] = run - base_b;
-        info[3 * b + 2] = cnt_b;
-      }
-    }
-    const uint4* src4 = reinterpret_cast<const uint4*>(slice);
-    uint4* dst4 = reinterpret_cast<uint4*>(bitvec + static_cast<uint64_t>(b) * slice_words);
-    for (uint32_t i = tid; i < slice_words / 4u; i += BLOCK) dst4[i] = src4[i];
-    return;
-  }
-
-  const uint32_t key_base = b << sb;
-  const uint64_t pop = scan_emit<BLOCK>(slice, slice_words, key_base, stage, stage_cap, scratch, out,
-                                        base_b, mode, dbg_bitmap, dbg_prefix,
-                                        static_cast<uint64_t>(b) * slice_words);
-  if (mode == kEmit && tid == 0) {
-    info[3 * b] = base_b;
-    info[3 * b + 1] = pop;
-    info[3 * b + 2] = cnt_b;
-  }
-}
-
-// Emit from the bit-vector in HBM (after k_slice in kToBitVector mode): one
-// workgroup per kChunkWords-word chunk, whose exclusive prefix of set bits
-// k_slice already wrote.  Each wave owns a quarter of the chunk, loads its
-// words into registers (4 per lane), counts them, and after one barrier emits
-// 64 words at a time exactly like scan_emit: straight stores for sparse and
-// full-word groups, otherwise an LDS window of kEmitWindow keys per wave.
-// Small LDS and small workgroups keep 32 waves on every CU.
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_emit(const uint32_t* __restrict__ bitvec,
-                                                const uint64_t* __restrict__ chunk_base,
-                                                uint32_t* __restrict__ out, int mode, uint64_t* dbg_prefix) {
-  constexpr uint32_t kWaves = BLOCK / kWave;
-  constexpr uint32_t kPer = kChunkWords / kWaves;  // words per wave
-  constexpr uint32_t kGroups = kPer / kWave;       // 64-word groups per wave
-  __shared__ uint32_t scratch[kWaves];
-  __shared__ __align__(16) uint32_t stage[kWaves * (kEmitWindow + 4)];
-  const uint32_t lane = threadIdx.x & (kWave - 1);
-  const uint32_t wave = threadIdx.x / kWave;
-  const uint64_t w_lo = static_cast<uint64_t>(blockIdx.x) * kChunkWords + wave * kPer;
-  uint32_t x[kGroups];
-  uint32_t cnt = 0;
-#pragma unroll
-  for (uint32_t g = 0; g < kGroups; ++g) {
-    x[g] = bitvec[w_lo + g * kWave + lane];
-    cnt += static_cast<uint32_t>(__popc(x[g]));
-  }
-  cnt = wave_sum_u32(cnt);
-  if (lane == 0) scratch[wave] = cnt;
-  __syncthreads();
-  uint64_t D = chunk_base[blockIdx.x];
-#pragma unroll
-  for (uint32_t i = 0; i < kWaves; ++i) D += (i < wave) ? scratch[i] : 0u;
-  D = uniform(D);
-  uint32_t* ws = stage + wave * (kEmitWindow + 4);
-#pragma unroll
-  for (uint32_t g = 0; g < kGroups; ++g) {
-    const uint64_t gw = w_lo + g * kWave + lane;  // global word index: its keys are 32*gw + bit
-    const uint32_t xg = x[g];
-    const uint32_t c = static_cast<uint32_t>(__popc(xg));
-    if (mode == kEmit) {
-      const uint64_t nz = __ballot(c != 0u);
-      if (nz == 0) continue;
-      if (__ballot(c > 1u) == 0) {
-        if (c != 0u) out[D + count_below(nz)] = static_cast<uint32_t>(gw << 5) + static_cast<uint32_t>(__builtin_ctz(xg));
-        D += static_cast<uint32_t>(__popcll(nz));
-        continue;
-      }
-      if (__ballot(xg != 0xFFFFFFFFu) == 0) {
-        const uint32_t kb0 = static_cast<uint32_t>((w_lo + g * kWave) << 5);
-#pragma unroll 8
-        for (uint32_t j = 0; j < 32; ++j) out[D + j * kWave + lane] = kb0 + j * kWave + lane;
-        D += 32u * kWave;
-        continue;
-      }
-    }
-    uint32_t tot;
-    const uint32_t p = wave_prefix_small(c, &tot);
-    tot = uniform(tot);
-    if (mode == kDumpPrefix) {
-      dbg_prefix[gw] = D + p;
-    } else if (mode == kEmit) {
-      for (uint32_t lo = 0; lo < tot; lo += kEmitWindow) {
-        uint32_t* dst = out + D + lo;
-        const uint32_t shift = static_cast<uint32_t>((reinterpret_cast<uintptr_t>(dst) >> 2) & 3u);
-        if (c != 0u && p < lo + kEmitWindow && p + c > lo) {
-          uint32_t y = xg, pos = p;
-          while (pos < lo) {
-            y &= y - 1u;
-            ++pos;
-          }
-          const uint32_t kb = static_cast<uint32_t>(gw << 5);
-          while (y != 0u && pos < lo + kEmitWindow) {
-            ws[shift + pos - lo] = kb + static_cast<uint32_t>(__builtin_ctz(y));
-            y &= y - 1u;
-            ++pos;
-          }
-        }
-        wave_sync();
-        wave_copy_out(ws, shift, dst, min(kEmitWindow, tot - lo));
-        wave_sync();
-      }
-    }
-    D += tot;
-  }
-}
-
-// Status of a two-kernel sort, after k_slice: flags, number of keys written,
-// and the compaction a duplicate calls for.  One workgroup.
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_finish(uint64_t n, uint32_t nb, const uint64_t* __restrict__ info,
-                                                  Status* status, uint32_t* out) {
-  __shared__ uint64_t scratch64[BLOCK / kWave];
-  uint64_t pop = 0, dup = 0;
-  for (uint32_t b = threadIdx.x; b < nb; b += BLOCK) {
-    const uint64_t p = info[3 * b + 1];
-    pop += p;
-    dup += (p != info[3 * b + 2]) ? 1u : 0u;
-  }
-  pop = block_sum_u64<BLOCK>(pop, scratch64);
-  dup = block_sum_u64<BLOCK>(dup, scratch64);
-  const uint64_t valid = uniform(info[3 * (nb - 1)] + info[3 * (nb - 1) + 2]);  // keys below 2^range_bits
-  if (threadIdx.x == 0) {
-    uint32_t f = 0;
-    if (valid != n) f |= BITSORT_STATUS_OUT_OF_RANGE;
-    if (dup != 0) f |= BITSORT_STATUS_DUPLICATE;
-    status->flags = f;
-    status->done = 0;
-    status->count = pop;
-  }
-  if (dup != 0) compact_slices<BLOCK>(out, info, nb);
-}
-
-// ---------------------------------------------------------------------------
-// Direct: one workgroup, the key range fits one LDS slice (range <= 2^sb).
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_direct(const uint32_t* __restrict__ keys, uint64_t n,
-                                                  uint64_t range, uint32_t sb, uint32_t stage_cap,
-                                                  uint32_t* out, Status* status, int mode,
-                                                  uint32_t* dbg_bitmap, uint64_t* dbg_prefix) {
-  extern __shared__ __align__(16) uint32_t lds[];
-  uint64_t* scratch64 = reinterpret_cast<uint64_t*>(lds);
-  uint32_t* scratch = lds + 32;
-  uint32_t* slice = lds + 64;
-  const uint32_t slice_words = (sb >= 5) ? (1u << (sb - 5)) : 1u;
-  uint32_t* stage = slice + round_up4(slice_words);
-  const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < slice_words; i += BLOCK) slice[i] = 0u;
-  __syncthreads();
-  uint64_t valid = 0;
-  for (uint64_t i = tid; i < n; i += BLOCK) {
-    const uint32_t key = keys[i];
-    if (static_cast<uint64_t>(key) < range) {
-      ++valid;
-      atomicOr(&slice[key >> 5], 1u << (key & 31u));
-    }
-  }
-  valid = block_sum_u64<BLOCK>(valid, scratch64);  // also orders marks before the scan
-  const uint64_t pop = scan_emit<BLOCK>(slice, slice_words, 0u, stage, stage_cap, scratch, out, 0,
-                                        mode, dbg_bitmap, dbg_prefix, 0);
-  if (mode == kEmit && tid == 0) {
-    uint32_t f = 0;
-    if (valid != n) f |= BITSORT_STATUS_OUT_OF_RANGE;
-    if (pop != valid) f |= BITSORT_STATUS_DUPLICATE;
-    status->flags = f;
-    status->done = 0;
-    status->count = pop;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Seeded keyed permutation of [0, 2^bits) (synthetic inputs): 4-round
-// balanced Feistel network over d = bits rounded up to even, with cycle
-// walking back into [0, 2^bits) when bits is odd.
-__device__ __forceinline__ uint32_t feistel_round(uint32_t r, uint32_t k) {
-  uint32_t x = r ^ k;
-  x *= 0x9E3779B1u;
-  x ^= x >> 15;
-  x *= 0x85EBCA77u;
-  x ^= x >> 13;
-  return x;
-}
-
-__device__ __forceinline__ uint32_t feistel_even(uint32_t x, uint32_t d, uint32_t k0, uint32_t k1,
-                                                 uint32_t k2, uint32_t k3) {
-  const uint32_t h = d >> 1;
-  const uint32_t m = (1u << h) - 1u;
-  uint32_t left = x >> h, right = x & m;
-  const uint32_t rk[4] = {k0, k1, k2, k3};
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const uint32_t t = right;
-    right = left ^ (feistel_round(right, rk[i]) & m);
-    left = t;
-  }
-  return (left << h) | right;
-}
-
-__global__ void k_generate(uint32_t* __restrict__ out, uint64_t first, uint64_t count, uint32_t bits,
-                           uint32_t k0, uint32_t k1, uint32_t k2, uint32_t k3) {
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  const uint32_t d = bits + (bits & 1u);
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) {
-    if (bits == 0) {
-      out[i] = 0u;
-      continue;
-    }
-    uint32_t y = feistel_even(static_cast<uint32_t>(first + i), d, k0, k1, k2, k3);
-    if (d != bits) {
-      // Cycle walking ends: the cycle through x returns to x < 2^bits.
-      const uint32_t lim = 1u << bits;
-      while (y >= lim) y = feistel_even(y, d, k0, k1, k2, k3);
-    }
-    out[i] = y;
-  }
-}
-
-
-// ---------------------------------------------------------------------------
-// Batch: many independent segments, one persistent launch.
-//
-// Work items are (segment, slice) pairs; a segment with range 2^rb has
-// 2^(rb - sbb) slices of 2^sbb bits (one if rb <= sbb).  k_batch_plan lays
-// the items out largest range first (so the long items start early) and
-// k_batch_run's workgroups pull items from an atomic counter until none is
-// left.  An item reads its whole segment, keeps the keys of its slice (LDS
-// mark), counts the keys below the slice -- with distinct keys that count is
-// the slice's output offset inside the segment -- then scans and emits like
-// k_slice.  No workgroup waits on another.
-
-struct SegStatus {
-  uint32_t flags;
-  uint32_t pad;
-  uint64_t count;
-};
-
-constexpr uint32_t kMaxBatchRangeBits = BITSORT_BATCH_MAX_RANGE_BITS;
-
-__global__ __launch_bounds__(1024) void k_batch_plan(const uint64_t* __restrict__ offsets,
-                                                     const uint8_t* __restrict__ rbits, uint32_t nseg,
-                                                     uint64_t max_keys, uint32_t sbb,
-                                                     uint2* __restrict__ items,
-                                                     uint32_t* __restrict__ counter,
-                                                     SegStatus* __restrict__ seg_status) {
-  __shared__ uint32_t cls_items[kMaxBatchRangeBits + 1];
-  __shared__ uint32_t cls_cursor[kMaxBatchRangeBits + 1];
-  const uint32_t tid = threadIdx.x;
-  if (tid <= kMaxBatchRangeBits) cls_items[tid] = 0u;
-  __syncthreads();
-  for (uint32_t s = tid; s < nseg; s += blockDim.x) {
-    seg_status[s].flags = 0u;
-    seg_status[s].pad = 0u;
-    seg_status[s].count = 0ull;
-    const uint32_t rb = rbits[s];
-    if (rb > kMaxBatchRangeBits || offsets[s + 1] < offsets[s] || offsets[s + 1] > max_keys) continue;
-    const uint32_t ns = rb > sbb ? (1u << (rb - sbb)) : 1u;
-    atomicAdd(&cls_items[rb], ns);
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t run = 0;
-    for (int c = static_cast<int>(kMaxBatchRangeBits); c >= 0; --c) {  // widest ranges first
-      cls_cursor[c] = run;
-      run += cls_items[c];
-    }
-    counter[0] = 0u;
-    counter[1] = run;
-  }
-  __syncthreads();
-  for (uint32_t s = tid; s < nseg; s += blockDim.x) {
-    const uint32_t rb = rbits[s];
-    if (rb > kMaxBatchRangeBits || offsets[s + 1] < offsets[s] || offsets[s + 1] > max_keys) {
-      seg_status[s].flags = BITSORT_STATUS_BAD_SEGMENT;
-      continue;
-    }
-    const uint32_t ns = rb > sbb ? (1u << (rb - sbb)) : 1u;
-    const uint32_t pos = atomicAdd(&cls_cursor[rb], ns);
-    for (uint32_t j = 0; j < ns; ++j) items[pos + j] = make_uint2(s, j);
-  }
-}
-
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_batch_run(const uint32_t* __restrict__ keys,
-                                                     const uint64_t* __restrict__ offsets,
-                                                     const uint8_t* __restrict__ rbits, uint32_t sbb,
-                                                     uint32_t stage_cap, const uint2* __restrict__ items,
-                                                     uint32_t* counter, uint32_t* __restrict__ out,
-                                                     SegStatus* seg_status) {
-  extern __shared__ __align__(16) uint32_t lds[];
-  uint64_t* scratch64 = reinterpret_cast<uint64_t*>(lds);
-  uint32_t* scratch = lds + 32;
-  uint32_t* slice = lds + 64;
-  const uint32_t max_words = sbb >= 5 ? (1u << (sbb - 5)) : 1u;
-  uint32_t* stage = slice + round_up4(max_words);
-  const uint32_t tid = threadIdx.x;
-  const uint32_t total = uniform(__hip_atomic_load(&counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  for (;;) {
-    if (tid == 0) scratch[0] = atomicAdd(&counter[0], 1u);
-    __syncthreads();
-    const uint32_t it = uniform(scratch[0]);
-    __syncthreads();
-    if (it >= total) break;  // every workgroup leaves once the items run out
-    const uint2 item = items[it];
-    const uint32_t s = uniform(item.x), j = uniform(item.y);
-    const uint64_t lo = uniform(offsets[s]), hi = uniform(offsets[s + 1]);
-    const uint32_t rb = uniform(static_cast<uint32_t>(rbits[s]));
-    const uint32_t sb = min(rb, sbb);
-    const uint32_t words = sb >= 5 ? (1u << (sb - 5)) : 1u;
-    const uint64_t range = 1ull << rb;
-    for (uint32_t i = tid; i < words; i += BLOCK) slice[i] = 0u;
-    __syncthreads();
-    uint64_t below = 0, mine = 0, valid = 0;
-    const uint32_t smask = (1u << sb) - 1u;
-    uint64_t i = lo + tid;
-    for (; i + 3ull * BLOCK < hi; i += 4ull * BLOCK) {
-      uint32_t kq[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) kq[q] = keys[i + static_cast<uint64_t>(q) * BLOCK];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t key = kq[q];
-        if (static_cast<uint64_t>(key) < range) {
-          ++valid;
-          const uint32_t sl = key >> sb;
-          below += sl < j ? 1u : 0u;
-          if (sl == j) {
-            ++mine;
-            const uint32_t l = key & smask;
-            atomicOr(&slice[l >> 5], 1u << (l & 31u));
-          }
-        }
-      }
-    }
-    for (; i < hi; i += BLOCK) {
-      const uint32_t key = keys[i];
-      if (static_cast<uint64_t>(key) < range) {
-        ++valid;
-        const uint32_t sl = key >> sb;
-        below += sl < j ? 1u : 0u;
-        if (sl == j) {
-          ++mine;
-          const uint32_t l = key & smask;
-          atomicOr(&slice[l >> 5], 1u << (l & 31u));
-        }
-      }
-    }
-    below = block_sum_u64<BLOCK>(below, scratch64);
-    mine = block_sum_u64<BLOCK>(mine, scratch64);
-    valid = block_sum_u64<BLOCK>(valid, scratch64);
-    const uint64_t pop = scan_emit<BLOCK>(slice, words, j << sb, stage, stage_cap, scratch, out, lo + below,
-                                          kEmit, nullptr, nullptr, 0);
-    if (tid == 0) {
-      uint32_t f = 0;
-      if (pop != mine) f |= BITSORT_STATUS_DUPLICATE;
-      if (j == 0 && valid != hi - lo) f |= BITSORT_STATUS_OUT_OF_RANGE;
-      if (f) atomicOr(&seg_status[s].flags, f);
-      atomicAdd(reinterpret_cast<unsigned long long*>(&seg_status[s].count),
-                static_cast<unsigned long long>(pop));
-    }
-    __syncthreads();  // close the single-lane region before the next item's ticket
-  }
-}
+#include "batch_kernels.inc"
 
 // ---------------------------------------------------------------------------
 // Host side.
@@ -1671,20 +947,23 @@ int bitsort_serve_run(const bitsort_request_t* requests, uint32_t count, const b
     serve::SimExecutor ex(c.sim_overhead_s, c.sim_keys_per_s);
     return serve::schedule(ex, arena, requests, count, c, results, stats, true);
   }
+  if (reinterpret_cast<uintptr_t>(c.arena) % 256 != 0) return BITSORT_ERR_INVALID_ARG;
   int rc = init_kernels();
   if (rc != BITSORT_OK) return rc;
-  void* base = nullptr;
-  if (hipMalloc(&base, c.budget_bytes) != hipSuccess) {
+  void* base = c.arena;
+  if (base == nullptr && hipMalloc(&base, c.budget_bytes) != hipSuccess) {
     (void)hipGetLastError();
     return BITSORT_ERR_NO_MEMORY;
   }
   {
-    serve::HipExecutor ex;
+    serve::HipExecutor ex;  // its destructor waits for every slot stream
     rc = ex.init(static_cast<char*>(base), c.streams, c.verify != 0, c.max_batch_requests);
     if (rc == BITSORT_OK) rc = serve::schedule(ex, arena, requests, count, c, results, stats, false);
   }
-  (void)hipDeviceSynchronize();
-  (void)hipFree(base);
+  if (c.arena == nullptr) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(base);
+  }
   return rc;
 }
 

@@ -8,10 +8,12 @@ checks the two bit for bit.
 Generators
 ----------
 * ``keyed_permutation`` -- a seeded bijection pi on [0, 2^bits): a 4-round
-  balanced Feistel network (Luby-Rackoff construction) over an even number of
-  bits, with cycle walking (Black-Rogaway) when ``bits`` is odd.  Round keys
-  come from SplitMix64 (Steele, Lea, Flood 2014).  The round function is a
-  multiply / xor-shift mix.
+  Feistel network (Luby-Rackoff construction) whose halves have ceil(bits/2)
+  and floor(bits/2) bits and trade places every round (an alternating
+  unbalanced network; balanced when ``bits`` is even), so any ``bits`` maps
+  onto itself without cycle walking.  Round keys come from SplitMix64
+  (Steele, Lea, Flood 2014).  The round function is a multiply / xor-shift
+  mix.
 * ``distinct_uniform(n, bits, seed)`` = pi(0), ..., pi(n-1): n distinct keys in
   [0, 2^bits) in pseudo-random order ("uniform without replacement").
 * ``dense_permutation(bits, seed)`` = pi over all of [0, 2^bits).
@@ -61,15 +63,20 @@ def _round_fn(r: np.ndarray, k: int) -> np.ndarray:
     return x
 
 
-def _feistel_even(x: np.ndarray, bits: int, rkeys) -> np.ndarray:
-    """Balanced Feistel permutation of [0, 2^bits), bits even and >= 2."""
-    h = np.uint64(bits // 2)
-    m = np.uint64((1 << (bits // 2)) - 1)
-    left = x >> h
-    right = x & m
+def _feistel(x: np.ndarray, bits: int, rkeys) -> np.ndarray:
+    """Feistel permutation of [0, 2^bits), 1 <= bits <= 32.
+
+    The state is (left, right) with a = bits - bits//2 and b = bits//2 bits.
+    A round maps (left, right) to (right, left ^ (F(right) mod 2^a)); the
+    halves then hold b and a bits.  Each round is invertible, and after the
+    (even) number of rounds the widths are back to (a, b)."""
+    a, b = bits - bits // 2, bits // 2
+    left = x >> np.uint64(b)
+    right = x & np.uint64((1 << b) - 1)
     for k in rkeys:
-        left, right = right, left ^ (_round_fn(right, k) & m)
-    return (left << h) | right
+        left, right = right, left ^ (_round_fn(right, k) & np.uint64((1 << a) - 1))
+        a, b = b, a
+    return (left << np.uint64(b)) | right
 
 
 def keyed_permutation(idx, bits: int, seed: int) -> np.ndarray:
@@ -79,16 +86,7 @@ def keyed_permutation(idx, bits: int, seed: int) -> np.ndarray:
     idx = np.asarray(idx, dtype=np.uint64)
     if bits == 0:
         return np.zeros(idx.shape, dtype=np.uint32)
-    rkeys = feistel_round_keys(seed)
-    d = bits if bits % 2 == 0 else bits + 1
-    y = _feistel_even(idx, d, rkeys)
-    if d != bits:
-        limit = np.uint64(1 << bits)
-        bad = np.nonzero(y >= limit)[0]
-        while bad.size:
-            y[bad] = _feistel_even(y[bad], d, rkeys)
-            bad = bad[y[bad] >= limit]
-    return y.astype(np.uint32)
+    return _feistel(idx, bits, feistel_round_keys(seed)).astype(np.uint32)
 
 
 def distinct_uniform(n: int, bits: int, seed: int, chunk: int = 1 << 22) -> np.ndarray:

@@ -16,13 +16,13 @@ REQUEST = np.dtype([("n", "<u8"), ("range_bits", "<u4"), ("pad", "<u4"), ("seed"
                     ("arrival_s", "<f8")])
 RESULT = np.dtype([("launch_s", "<f8"), ("ready_s", "<f8"), ("done_s", "<f8"), ("digest", "<u8"),
                    ("count", "<u8"), ("flags", "<u4"), ("batch", "<u4")])
-CONFIG = np.dtype([("budget_bytes", "<u8"), ("streams", "<u4"), ("max_batch_requests", "<u4"),
+CONFIG = np.dtype([("arena", "<u8"), ("budget_bytes", "<u8"), ("streams", "<u4"), ("max_batch_requests", "<u4"),
                    ("max_batch_keys", "<u8"), ("plain_range_bits", "<u4"), ("verify", "<u4"), ("simulate", "<u4"),
                    ("pad", "<u4"),
                    ("sim_overhead_s", "<f8"), ("sim_keys_per_s", "<f8")])
 STATS = np.dtype([("makespan_s", "<f8"), ("keys", "<u8"), ("launches", "<u4"),
                   ("max_inflight_requests", "<u4"), ("peak_bytes", "<u8")])
-assert REQUEST.itemsize == 32 and RESULT.itemsize == 48 and CONFIG.itemsize == 56 and STATS.itemsize == 32
+assert REQUEST.itemsize == 32 and RESULT.itemsize == 48 and CONFIG.itemsize == 64 and STATS.itemsize == 32
 
 
 def make_trace(count: int, lo: int, hi: int, rate_per_s: float, seed: int, factor: int = 4) -> np.ndarray:
@@ -37,13 +37,40 @@ def make_trace(count: int, lo: int, hi: int, rate_per_s: float, seed: int, facto
     return req
 
 
-def run(requests: np.ndarray, budget_bytes: int, streams: int = 2, max_batch_requests: int = 4096,
+_ARENA = {}
+
+
+def _arena(budget_bytes: int):
+    """A torch-allocated arena, kept for later calls with the same budget."""
+    import torch
+    t = _ARENA.get(budget_bytes)
+    if t is None:
+        _ARENA.clear()
+        t = _ARENA[budget_bytes] = torch.empty(budget_bytes, dtype=torch.uint8, device="cuda")
+    return t
+
+
+def release_arena() -> None:
+    _ARENA.clear()
+
+
+def run(requests: np.ndarray, budget_bytes: int, streams: int = 4, max_batch_requests: int = 4096,
         max_batch_keys: int = 1 << 26, plain_range_bits: int = 0, verify: bool = False, simulate: bool = False,
-        sim_overhead_s: float = 20e-6, sim_keys_per_s: float = 2e11):
-    """Run the trace; returns (results array, stats dict)."""
+        sim_overhead_s: float = 20e-6, sim_keys_per_s: float = 2e11, arena=None):
+    """Run the trace; returns (results array, stats dict).
+
+    The arena is ``arena`` (a uint8 device tensor of at least budget_bytes)
+    or a torch allocation cached across calls; nothing is allocated when
+    ``simulate`` is set."""
     requests = np.ascontiguousarray(requests, dtype=REQUEST)
     res = np.zeros(max(len(requests), 1), dtype=RESULT)
     cfg = np.zeros(1, dtype=CONFIG)
+    if not simulate:
+        if arena is None:
+            arena = _arena(budget_bytes)
+        if arena.numel() * arena.element_size() < budget_bytes:
+            raise ValueError("arena is smaller than budget_bytes")
+        cfg["arena"] = arena.data_ptr()
     cfg["budget_bytes"] = budget_bytes
     cfg["streams"] = streams
     cfg["max_batch_requests"] = max_batch_requests
@@ -66,6 +93,8 @@ def summarize(requests: np.ndarray, results: np.ndarray, stats: dict) -> dict:
     wait = (results["launch_s"] - requests["arrival_s"])[ok]
     gen = (results["ready_s"] - results["launch_s"])[ok]
     keys = int(results["count"][ok].sum())
+    per_launch = np.bincount(results["batch"][ok].astype(np.int64)) if ok.any() else np.zeros(0, np.int64)
+    per_launch = per_launch[per_launch > 0]
     return {
         "requests": int(len(requests)), "served": int(ok.sum()), "rejected": int((~ok).sum()),
         "keys": keys, "makespan_s": stats["makespan_s"],
@@ -76,6 +105,9 @@ def summarize(requests: np.ndarray, results: np.ndarray, stats: dict) -> dict:
         "mean_launch_to_keys_ready_ms": float(gen.mean() * 1e3) if gen.size else None,
         "keys_ready_share_of_latency": float(gen.sum() / lat.sum()) if lat.size and lat.sum() > 0 else None,
         "launches": stats["launches"], "max_inflight_requests": stats["max_inflight_requests"],
+        "requests_per_launch": ({"mean": float(per_launch.mean()), "max": int(per_launch.max()),
+                                 "hist_pow2": np.bincount(np.log2(per_launch).astype(np.int64)).tolist()}
+                                if per_launch.size else None),
         "peak_bytes": stats["peak_bytes"],
     }
 
