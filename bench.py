@@ -16,6 +16,9 @@ Workloads (default: plain-uniform):
   plain-clustered keys from 64 Gaussian clusters (sigma 2^16) in [0, 2^28)
   plain-dense     a permutation of all of [0, 2^28)
   plain-sparse    2^24 distinct keys in [0, 2^32)
+  radix-uniform   2^26 uint32 keys uniform in [0, 2^32) with repeats, through
+                  the LSD radix sort (the paper's Algorithm 1, 8-bit digits)
+  radix-sparse    the plain-sparse input through the LSD radix sort
   batch           4096 arrays, sizes log-uniform in [256, 2^20], range the
                   power of two >= 4n: one batched launch vs 4096 plain launches
   serve           20,000 sort requests, sizes log-uniform in [2^10, 2^24],
@@ -47,12 +50,17 @@ PLAIN = {
     "plain-clustered": dict(n=None, rb=28, cfg=2, desc="64 Gaussian clusters (sigma 2^16) in [0, 2^28), 2^26 draws de-duplicated"),
     "plain-dense": dict(n=1 << 28, rb=28, cfg=3, desc="permutation of all of [0, 2^28)"),
     "plain-sparse": dict(n=1 << 24, rb=32, cfg=3, desc="2^24 distinct uint32 keys uniform in [0, 2^32), 512 MiB bit-vector"),
+    "radix-uniform": dict(n=1 << 26, rb=32, cfg=6, sorter="radix",
+                          desc="2^26 uint32 keys uniform in [0, 2^32) with repeats; LSD radix, 4 passes of 8-bit digits"),
+    "radix-sparse": dict(n=1 << 24, rb=32, cfg=3, sorter="radix",
+                         desc="the plain-sparse input (2^24 distinct keys in [0, 2^32)) through the LSD radix sort"),
 }
 
 
 KERNEL_SOURCES = {
     "plain": ["bitsort_device.h", "plain_kernels.inc"],
     "batch": ["bitsort_device.h", "plain_kernels.inc", "batch_kernels.inc"],
+    "radix": ["bitsort_device.h", "radix_kernels.inc"],
 }
 
 
@@ -83,6 +91,13 @@ def algorithmic_bytes(n: int, rb: int, emit_path: str) -> dict:
     return ab
 
 
+def radix_algorithmic_bytes(n: int, key_bits: int) -> dict:
+    """The LSD radix sort's own bytes: every digit pass reads and writes the
+    n keys once (8n); the histogram pass and look-back state are overhead."""
+    passes = (key_bits + 7) // 8
+    return {"k_radix_pass": 8 * n, "k_radix_hist": 4 * n, "k_radix_scan": 0, "path": passes * 8 * n}
+
+
 def read_traffic(kernel: str, workload: str, digest: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when there is none or the kernel sources changed since."""
@@ -102,15 +117,19 @@ def read_traffic(kernel: str, workload: str, digest: str):
         return None
 
 
-def cpu_baseline(keys_host, rb: int, budget_s: float = 12.0, max_reps: int = 5):
-    """The oracle, single-threaded, timed on the host: (Gkeys/s, reps, out)."""
+def cpu_baseline(keys_host, rb: int, budget_s: float = 12.0, max_reps: int = 5, sorter: str = "bitmap"):
+    """The oracle, single-threaded, timed on the host: (Gkeys/s, reps, out).
+    The radix sort's oracle is the paper's Algorithm 1 over rb bit passes."""
     import oracle
     o = oracle.default()
     times, out = [], None
     t_start = time.perf_counter()
     for _ in range(max_reps):
         t0 = time.perf_counter()
-        out, _, _ = o.bitmap_sort(keys_host, rb)
+        if sorter == "radix":
+            out = o.bitwise_sort1(keys_host, rb)
+        else:
+            out, _, _ = o.bitmap_sort(keys_host, rb)
         times.append(time.perf_counter() - t0)
         if time.perf_counter() - t_start > budget_s:
             break
@@ -122,6 +141,11 @@ def make_plain_inputs(bs, torch, spec, workload, pool):
     from paper_1312_0138_amd import inputs
     n, rb, cfg = spec["n"], spec["rb"], spec["cfg"]
     bufs = []
+    if workload == "radix-uniform":
+        for rep in range(pool):
+            host = host_input(spec, workload, n, rep)
+            bufs.append(torch.from_numpy(host.view("int32")).cuda())
+        return bufs, n
     if workload == "plain-clustered":
         host = inputs.clustered(1 << 26, rb, inputs.config_seed(cfg, 1))
         n = host.size
@@ -135,9 +159,14 @@ def make_plain_inputs(bs, torch, spec, workload, pool):
     return bufs, n
 
 
-def host_input(spec, workload, n):
+def host_input(spec, workload, n, rep=0):
+    import numpy as np
+
     from paper_1312_0138_amd import inputs
     rb, cfg = spec["rb"], spec["cfg"]
+    if workload == "radix-uniform":
+        rng = np.random.default_rng(inputs.config_seed(cfg, rep))
+        return rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
     if workload == "plain-clustered":
         return inputs.clustered(1 << 26, rb, inputs.config_seed(cfg, 1))
     return inputs.distinct_uniform(n, rb, inputs.config_seed(cfg, 0))
@@ -152,6 +181,8 @@ def bench_plain(args, workload):
 
     spec = PLAIN[workload]
     rb = spec["rb"]
+    radix = spec.get("sorter") == "radix"
+    sort = bs.radix_sort if radix else bs.sort
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     pool = args.pool
@@ -160,11 +191,11 @@ def bench_plain(args, workload):
         pool = max(2, min(128, -(-2 * MALL_BYTES // per)))
     bufs, n = make_plain_inputs(bs, torch, spec, workload, pool)
     out = torch.empty(n, dtype=torch.int32, device="cuda")
-    tuned = bs.autotune(n, rb, reps=3) if args.autotune else None
-    plan = bs.plan_info(n, rb)
+    tuned = bs.autotune(n, rb, reps=3) if args.autotune and not radix else None
+    plan = None if radix else bs.plan_info(n, rb)
 
     graphs = None
-    if args.graph:
+    if args.graph and not radix:
         # one captured graph per input buffer: replays allocate and launch nothing else
         graphs = [bs.Graph.plain(b, rb, out) for b in bufs]
 
@@ -172,7 +203,7 @@ def bench_plain(args, workload):
         if graphs is not None:
             graphs[i % len(graphs)].launch()
         else:
-            bs.sort(bufs[i % len(bufs)], rb, out)
+            sort(bufs[i % len(bufs)], rb, out)
 
     for i in range(args.warmup):
         step(i)
@@ -206,7 +237,7 @@ def bench_plain(args, workload):
     torch.cuda.synchronize()
     for i in range(args.steps):
         starts[i].record(stream)
-        bs.sort(bufs[i % len(bufs)], rb, out)  # eager calls: kernels timed by library events
+        sort(bufs[i % len(bufs)], rb, out)  # eager calls: kernels timed by library events
         ends[i].record(stream)
     torch.cuda.synchronize()
     _lib.check(_lib.bitsort_profile_enable(False), "profile_enable")
@@ -218,11 +249,11 @@ def bench_plain(args, workload):
 
     ms_per_step = total_ms / args.steps
     value = n / (ms_per_step / 1e3) / 1e9
-    ab = algorithmic_bytes(n, rb, plan["emit_path"])
+    ab = radix_algorithmic_bytes(n, rb) if radix else algorithmic_bytes(n, rb, plan["emit_path"])
     kernels = {k: {"launches": int(l), "avg_us": round(1e3 * ms / max(l, 1), 3)} for k, (l, ms) in prof.items()}
     dom = max(prof, key=lambda k: prof[k][1])
     dom_avg_s = prof[dom][1] / prof[dom][0] / 1e3
-    digest = source_digest()
+    digest = source_digest("radix" if radix else "plain")
     achieved = ab[dom] / dom_avg_s / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
@@ -232,9 +263,11 @@ def bench_plain(args, workload):
         "metric": METRIC, "value": round(value, 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": workload, "description": spec["desc"], "n": n, "range_bits": rb,
-                   "input_pool": len(bufs), "slice_bits": plan["slice_bits"], "tile_log2": plan["tile_log2"],
-                   "slices": plan["buckets"], "emit_path": plan["emit_path"]},
+        "config": ({"workload": workload, "description": spec["desc"], "n": n, "key_bits": rb,
+                    "input_pool": len(bufs), "passes": (rb + 7) // 8} if radix else
+                   {"workload": workload, "description": spec["desc"], "n": n, "range_bits": rb,
+                    "input_pool": len(bufs), "slice_bits": plan["slice_bits"], "tile_log2": plan["tile_log2"],
+                    "slices": plan["buckets"], "emit_path": plan["emit_path"]}),
         "p50_ms": round(p50, 5), "p99_ms": round(p99, 5),
         "profiled_ms_per_step": round(sum(step_ms) / len(step_ms), 5),
         "roofline": roofline,
@@ -246,16 +279,17 @@ def bench_plain(args, workload):
     }
     if not args.no_cpu_baseline:
         keys_host = host_input(spec, workload, n)
-        gk, reps, med, want = cpu_baseline(keys_host, rb)
+        gk, reps, med, want = cpu_baseline(keys_host, rb, sorter="radix" if radix else "bitmap")
         # the GPU result for the same input must equal the oracle's
         check_in = torch.from_numpy(keys_host.view(np.int32)).cuda()
-        got = bs.sort(check_in, rb).cpu().numpy().view(np.uint32)
+        got = sort(check_in, rb).cpu().numpy().view(np.uint32)
         if not np.array_equal(got, want):
             print(json.dumps({"error": "GPU output differs from the CPU oracle", "workload": workload}))
             sys.exit(3)
         result["cpu_baseline"] = {"value": round(gk, 4), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
                                   "sample": f"full {workload} input (n={n}), {reps} repetition(s), "
-                                            f"median {med:.3f} s per sort; single-threaded C oracle",
+                                            f"median {med:.3f} s per sort; single-threaded C oracle"
+                                            + (" (Algorithm 1, 32 one-bit passes)" if radix else ""),
                                   "host_cores": os.cpu_count()}
         result["verified_against_oracle"] = True
     return result

@@ -54,6 +54,7 @@ typedef void *bitsort_stream_t; /* a hipStream_t */
 /* Device status flags (bitsort_status_t.flags). */
 #define BITSORT_STATUS_OUT_OF_RANGE 1u /* some key was >= 2^range_bits and was dropped */
 #define BITSORT_STATUS_DUPLICATE 2u    /* some key occurred more than once */
+#define BITSORT_STATUS_TIMEOUT 32u     /* a bounded wait between workgroups gave up: the output is invalid */
 
 typedef struct bitsort_status {
     uint32_t flags;  /* BITSORT_STATUS_* bits */
@@ -83,6 +84,18 @@ const char *bitsort_error_string(int code);
  */
 int bitsort_u32(const uint32_t *keys, uint64_t n, uint32_t range_bits, uint32_t *out,
                 bitsort_stream_t stream);
+
+/*
+ * The same bitmap sort for signed keys (the paper sorts any integer type,
+ * negative keys included: Section V's BitwiseSort puts the negative keys
+ * first).  Keys are distinct int32 in [-2^(range_bits-1), 2^(range_bits-1))
+ * (range_bits 1..32; 0 allows only the key 0).  Each key is shifted by
+ * 2^(range_bits-1) on load, which maps that range onto [0, 2^range_bits) in
+ * order, and shifted back on output, inside the same kernels: no extra pass.
+ * Arguments, errors, status and workspace as bitsort_u32; a key outside the
+ * signed range is dropped and raises BITSORT_STATUS_OUT_OF_RANGE.
+ */
+int bitsort_i32(const int32_t *keys, uint64_t n, uint32_t range_bits, int32_t *out, bitsort_stream_t stream);
 
 /* Bytes of caller workspace bitsort_u32_ws needs for (n, range_bits); 0 on
  * invalid arguments. */
@@ -136,6 +149,72 @@ int bitsort_batch_u32(const uint32_t *keys, const uint64_t *offsets, uint32_t nu
 /* Synchronise `stream`, then copy per-segment statuses of the last
  * bitsort_batch_u32 on it into host status[0 .. num_segments). */
 int bitsort_batch_status(bitsort_stream_t stream, bitsort_status_t *status, uint32_t num_segments);
+
+/*
+ * LSD radix sort of arbitrary uint32 keys, duplicates kept: the paper's own
+ * sort (Algorithm 1, Section V; correctness by Theorem 1), a stable partition
+ * by each key bit from bit 0 up, run here as ceil(key_bits / 8) stable passes
+ * over 8-bit digits (eight consecutive one-bit stable partitions order the
+ * keys exactly as one stable pass over their 8-bit digit).
+ *
+ *   keys      device pointer to n uint32 keys (any values; read only).
+ *   n         number of keys, n < 2^30.
+ *   key_bits  0..32: the keys are ordered by their low key_bits bits, stably
+ *             (the order Algorithm 1 gives after key_bits passes).  A key
+ *             with a bit set at or above key_bits raises
+ *             BITSORT_STATUS_OUT_OF_RANGE; it is still written, placed by its
+ *             low bits.  Use 32 for arbitrary keys.
+ *   out       device pointer to n uint32 (written): the keys in that order.
+ *             out == keys is allowed; any other overlap is rejected.
+ *   stream    HIP stream; the call only enqueues work.
+ *
+ * Status (bitsort_get_status on the same stream): count = n, flags as above;
+ * BITSORT_STATUS_TIMEOUT if a workgroup's wait for an earlier one gave up.
+ * Errors: BITSORT_ERR_INVALID_ARG (key_bits > 32, null pointers with n > 0,
+ * partial overlap), BITSORT_ERR_TOO_LARGE (n >= 2^30), BITSORT_ERR_NO_MEMORY.
+ * Workspace: grown per stream like bitsort_u32's (4n bytes plus n/8 bytes of
+ * look-back state per pass); the _ws form takes the caller's (256-byte
+ * aligned, bitsort_radix_workspace_bytes(n, key_bits) bytes, status readable
+ * with bitsort_workspace_status).
+ */
+int bitsort_radix_u32(const uint32_t *keys, uint64_t n, uint32_t key_bits, uint32_t *out, bitsort_stream_t stream);
+size_t bitsort_radix_workspace_bytes(uint64_t n, uint32_t key_bits);
+int bitsort_radix_u32_ws(const uint32_t *keys, uint64_t n, uint32_t key_bits, uint32_t *out, void *workspace,
+                         size_t ws_bytes, bitsort_stream_t stream);
+
+/*
+ * Multiset sort by counting: keys in [0, 2^range_bits) that may repeat,
+ * written out ascending with every repeat kept (counting sort, which the
+ * paper sets beside its own method; the result equals Algorithm 1's for
+ * in-range keys).  The bitmap path's partition routes keys to slices of
+ * 2^sb keys; each slice keeps one 32-bit counter per key in LDS instead of
+ * one bit, and writes each key as many times as it was counted.
+ *
+ *   keys        device pointer to n uint32 keys (read only).
+ *   n           number of keys, n < 2^32.
+ *   range_bits  0..27 (at most 2^12 slices of 2^15 counters).
+ *   out         device pointer to n uint32: out[0..count) receives the kept
+ *               keys ascending with repeats; out == keys is allowed, any other
+ *               overlap is rejected.
+ *   stream      HIP stream; the call only enqueues work.
+ *
+ * Keys >= 2^range_bits are dropped and raise BITSORT_STATUS_OUT_OF_RANGE
+ * (out[count..n) is then left unspecified); count = number of kept keys.
+ * Status with bitsort_get_status on the same stream.  Errors:
+ * BITSORT_ERR_INVALID_ARG (range_bits > 27, null pointers with n > 0, partial
+ * overlap), BITSORT_ERR_TOO_LARGE (n >= 2^32), BITSORT_ERR_NO_MEMORY.
+ */
+int bitsort_count_u32(const uint32_t *keys, uint64_t n, uint32_t range_bits, uint32_t *out, bitsort_stream_t stream);
+
+/*
+ * LSD radix sort of arbitrary int32 keys, duplicates kept: the order of the
+ * paper's BitwiseSort (Section V: negative keys first, each sign group sorted
+ * by BitwiseSort1 over its low 31 bits), which is the order of the keys with
+ * their sign bit flipped read as unsigned.  The digits are taken from
+ * key ^ 2^31; the keys themselves move unchanged.  Four passes; arguments,
+ * errors, status and workspace as bitsort_radix_u32 with key_bits = 32.
+ */
+int bitsort_radix_i32(const int32_t *keys, uint64_t n, int32_t *out, bitsort_stream_t stream);
 
 /*
  * Device-side input generator (the synthetic workloads): out[i] = pi(first + i)
@@ -319,7 +398,8 @@ int bitsort_digest_u32(const uint32_t *data, uint64_t n, uint64_t *digest, bitso
  * Enabling costs two event records per kernel launch.
  */
 typedef struct bitsort_profile_entry {
-    char kernel[32];      /* k_partition, k_slice, k_emit, k_finish, k_direct, k_batch_plan, k_batch_run */
+    char kernel[32];      /* k_partition, k_slice, k_emit, k_finish, k_direct, k_batch_plan, k_batch_run,
+                             k_radix_hist, k_radix_scan, k_radix_pass, k_count_slice */
     uint64_t launches;
     double total_ms;
 } bitsort_profile_entry_t;

@@ -10,14 +10,14 @@ from __future__ import annotations
 
 from . import _lib
 from ._lib import (BitsortError, STATUS_BAD_SEGMENT, STATUS_DUPLICATE,
-                   STATUS_OUT_OF_RANGE, Status)
+                   STATUS_OUT_OF_RANGE, STATUS_TIMEOUT, Status)
 
 __all__ = [
     "sort", "status", "sort_batch", "batch_status", "generate", "debug_bitmap",
     "debug_prefix", "workspace_bytes", "sort_ws", "workspace_status", "set_tuning",
     "plan_info", "BitsortError", "Status", "STATUS_OUT_OF_RANGE", "STATUS_DUPLICATE",
     "STATUS_BAD_SEGMENT", "Graph", "autotune", "autotune_batch", "tuning_save", "tuning_load",
-    "tuning_clear",
+    "tuning_clear", "radix_sort", "radix_workspace_bytes", "radix_sort_ws", "STATUS_TIMEOUT", "sort_signed", "radix_sort_signed", "sort_multiset",
 ]
 
 
@@ -54,6 +54,86 @@ def sort(keys, range_bits: int, out=None, stream=None):
         raise ValueError("out must have as many elements as keys")
     _lib.check(_lib.bitsort_u32(keys.data_ptr(), keys.numel(), range_bits, out.data_ptr(), _stream(stream)),
                "bitsort_u32")
+    return out
+
+
+def radix_sort(keys, key_bits: int = 32, out=None, stream=None):
+    """Stable LSD radix sort (the paper's Algorithm 1 in 8-bit digits) of any
+    32-bit keys by their low ``key_bits`` bits; duplicates are kept."""
+    torch = _torch()
+    _check_u32(keys, "keys")
+    if out is None:
+        out = torch.empty_like(keys)
+    _check_u32(out, "out")
+    if out.numel() != keys.numel():
+        raise ValueError("out must have as many elements as keys")
+    _lib.check(_lib.bitsort_radix_u32(keys.data_ptr(), keys.numel(), key_bits, out.data_ptr(), _stream(stream)),
+               "bitsort_radix_u32")
+    return out
+
+
+def _check_i32(t, name):
+    torch = _torch()
+    if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous int32 device tensor")
+
+
+def sort_signed(keys, range_bits: int = 32, out=None, stream=None):
+    """Bitmap sort of distinct int32 keys in [-2^(range_bits-1), 2^(range_bits-1))."""
+    torch = _torch()
+    _check_i32(keys, "keys")
+    if out is None:
+        out = torch.empty_like(keys)
+    _check_i32(out, "out")
+    if out.numel() != keys.numel():
+        raise ValueError("out must have as many elements as keys")
+    _lib.check(_lib.bitsort_i32(keys.data_ptr(), keys.numel(), range_bits, out.data_ptr(), _stream(stream)),
+               "bitsort_i32")
+    return out
+
+
+def radix_sort_signed(keys, out=None, stream=None):
+    """Stable LSD radix sort of any int32 keys (negative keys first), duplicates kept."""
+    torch = _torch()
+    _check_i32(keys, "keys")
+    if out is None:
+        out = torch.empty_like(keys)
+    _check_i32(out, "out")
+    if out.numel() != keys.numel():
+        raise ValueError("out must have as many elements as keys")
+    _lib.check(_lib.bitsort_radix_i32(keys.data_ptr(), keys.numel(), out.data_ptr(), _stream(stream)),
+               "bitsort_radix_i32")
+    return out
+
+
+def sort_multiset(keys, range_bits: int, out=None, stream=None):
+    """Counting sort of keys in [0, 2^range_bits) (range_bits <= 27) keeping
+    repeats; status().count is the number of kept keys."""
+    torch = _torch()
+    _check_u32(keys, "keys")
+    if out is None:
+        out = torch.empty_like(keys)
+    _check_u32(out, "out")
+    if out.numel() != keys.numel():
+        raise ValueError("out must have as many elements as keys")
+    _lib.check(_lib.bitsort_count_u32(keys.data_ptr(), keys.numel(), range_bits, out.data_ptr(), _stream(stream)),
+               "bitsort_count_u32")
+    return out
+
+
+def radix_workspace_bytes(n: int, key_bits: int = 32) -> int:
+    return _lib.bitsort_radix_workspace_bytes(n, key_bits)
+
+
+def radix_sort_ws(keys, workspace, key_bits: int = 32, out=None, stream=None):
+    """``radix_sort`` with a caller workspace (a uint8 device tensor)."""
+    torch = _torch()
+    _check_u32(keys, "keys")
+    if out is None:
+        out = torch.empty_like(keys)
+    _lib.check(_lib.bitsort_radix_u32_ws(keys.data_ptr(), keys.numel(), key_bits, out.data_ptr(),
+                                         workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                         _stream(stream)), "bitsort_radix_u32_ws")
     return out
 
 

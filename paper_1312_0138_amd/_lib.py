@@ -20,6 +20,7 @@ BITSORT_ERR_HIP = 4
 STATUS_OUT_OF_RANGE = 1
 STATUS_DUPLICATE = 2
 STATUS_BAD_SEGMENT = 4
+STATUS_TIMEOUT = 32
 REQ_REJECTED = 8
 REQ_INVALID = 16
 
@@ -55,6 +56,12 @@ _SIGS = {
     "bitsort_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
     "bitsort_workspace_bytes": (_c.c_size_t, [_u64, _u32]),
     "bitsort_u32_ws": (_c.c_int, [_vp, _u64, _u32, _vp, _vp, _c.c_size_t, _vp]),
+    "bitsort_radix_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
+    "bitsort_radix_i32": (_c.c_int, [_vp, _u64, _vp, _vp]),
+    "bitsort_i32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
+    "bitsort_count_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
+    "bitsort_radix_workspace_bytes": (_c.c_size_t, [_u64, _u32]),
+    "bitsort_radix_u32_ws": (_c.c_int, [_vp, _u64, _u32, _vp, _vp, _c.c_size_t, _vp]),
     "bitsort_get_status": (_c.c_int, [_vp, _c.POINTER(Status)]),
     "bitsort_workspace_status": (_c.c_int, [_vp, _vp, _c.POINTER(Status)]),
     "bitsort_batch_u32": (_c.c_int, [_vp, _vp, _u32, _vp, _vp, _u64, _vp]),
@@ -142,6 +149,30 @@ def bitsort_workspace_bytes(n: int, range_bits: int) -> int:
 
 def bitsort_u32_ws(keys: int, n: int, range_bits: int, out: int, ws: int, ws_bytes: int, stream: int) -> int:
     return lib().bitsort_u32_ws(keys, n, range_bits, out, ws, ws_bytes, stream)
+
+
+def bitsort_radix_u32(keys: int, n: int, key_bits: int, out: int, stream: int) -> int:
+    return lib().bitsort_radix_u32(keys, n, key_bits, out, stream)
+
+
+def bitsort_radix_i32(keys: int, n: int, out: int, stream: int) -> int:
+    return lib().bitsort_radix_i32(keys, n, out, stream)
+
+
+def bitsort_count_u32(keys: int, n: int, range_bits: int, out: int, stream: int) -> int:
+    return lib().bitsort_count_u32(keys, n, range_bits, out, stream)
+
+
+def bitsort_i32(keys: int, n: int, range_bits: int, out: int, stream: int) -> int:
+    return lib().bitsort_i32(keys, n, range_bits, out, stream)
+
+
+def bitsort_radix_workspace_bytes(n: int, key_bits: int) -> int:
+    return lib().bitsort_radix_workspace_bytes(n, key_bits)
+
+
+def bitsort_radix_u32_ws(keys: int, n: int, key_bits: int, out: int, ws: int, ws_bytes: int, stream: int) -> int:
+    return lib().bitsort_radix_u32_ws(keys, n, key_bits, out, ws, ws_bytes, stream)
 
 
 def bitsort_get_status(stream: int) -> tuple[int, Status]:

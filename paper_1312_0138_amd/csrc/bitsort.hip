@@ -80,6 +80,12 @@ namespace {
 #include "batch_kernels.inc"
 
 // ---------------------------------------------------------------------------
+#include "radix_kernels.inc"
+
+// ---------------------------------------------------------------------------
+#include "count_kernels.inc"
+
+// ---------------------------------------------------------------------------
 // Host side.
 
 struct Plan {
@@ -90,6 +96,7 @@ struct Plan {
   size_t off_binfo = 0, off_table = 0, off_staging = 0, off_bitvec = 0, off_chunk = 0, bytes = 0;
   uint32_t stage_cap = 0;
   size_t slice_lds = 0;
+  uint32_t bias = 0;  // signed keys: added on load, subtracted on output (mod 2^32)
 };
 
 std::atomic<uint32_t> g_tune_sb{0};
@@ -215,6 +222,7 @@ int init_kernels() {
     set_lds_attr(k_partition<1024, 32>, kLdsBytes);
     set_lds_attr(k_slice<kSliceBlock, kSliceUnroll>, kLdsBytes);
     set_lds_attr(k_direct<kDirectBlock>, kLdsBytes);
+    set_lds_attr(k_count_slice<kSliceBlock, kSliceUnroll>, kLdsBytes);
     set_lds_attr(k_batch_run<256>, kLdsBytes);
     set_lds_attr(k_batch_run<512>, kLdsBytes);
     set_lds_attr(k_batch_run<1024>, kLdsBytes);
@@ -228,9 +236,13 @@ int launch_status() {
 }
 
 // Kernel timing (bitsort_profile_*): events bracketing each launch.
-enum KernelId : int { kKPartition = 0, kKSlice, kKEmit, kKFinish, kKDirect, kKBatchPlan, kKBatchRun, kKCount };
-const char* const kKernelNames[kKCount] = {"k_partition", "k_slice", "k_emit", "k_finish", "k_direct",
-                                           "k_batch_plan", "k_batch_run"};
+enum KernelId : int {
+  kKPartition = 0, kKSlice, kKEmit, kKFinish, kKDirect, kKBatchPlan, kKBatchRun, kKRadixHist, kKRadixScan,
+  kKRadixPass, kKCountSlice, kKCount
+};
+const char* const kKernelNames[kKCount] = {"k_partition", "k_slice",      "k_emit",       "k_finish",
+                                           "k_direct",    "k_batch_plan", "k_batch_run",  "k_radix_hist",
+                                           "k_radix_scan", "k_radix_pass", "k_count_slice"};
 struct PendingTiming {
   int kernel;
   hipEvent_t start, stop;
@@ -265,6 +277,34 @@ struct LaunchTimer {
 };
 
 // Enqueue the plain path.  mode != kEmit writes the debug dumps instead.
+// Partition launch shared by the bitmap and the counting path.
+int launch_partition(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* staging, uint32_t* table,
+                     hipStream_t stream) {
+  const uint64_t range = 1ull << p.rb;
+  const int vec_ok = (reinterpret_cast<uintptr_t>(keys) % 16u) == 0 ? 1 : 0;
+  const size_t part_lds = 4ull * (32 + round_up4(p.nb) + p.tile_keys);
+  LaunchTimer timer(kKPartition, stream);
+  switch (p.tile_log2) {
+    case 12:
+      hipLaunchKernelGGL((k_partition<256, 16>), dim3(p.nt), dim3(256), part_lds, stream, keys, n, range, p.sb, p.nb,
+                         staging, table, vec_ok, p.bias);
+      break;
+    case 13:
+      hipLaunchKernelGGL((k_partition<512, 16>), dim3(p.nt), dim3(512), part_lds, stream, keys, n, range, p.sb, p.nb,
+                         staging, table, vec_ok, p.bias);
+      break;
+    case 14:
+      hipLaunchKernelGGL((k_partition<1024, 16>), dim3(p.nt), dim3(1024), part_lds, stream, keys, n, range, p.sb,
+                         p.nb, staging, table, vec_ok, p.bias);
+      break;
+    default:
+      hipLaunchKernelGGL((k_partition<1024, 32>), dim3(p.nt), dim3(1024), part_lds, stream, keys, n, range, p.sb,
+                         p.nb, staging, table, vec_ok, p.bias);
+      break;
+  }
+  return launch_status();
+}
+
 int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, void* ws,
               hipStream_t stream, int mode, uint32_t* dbg_bitmap, uint64_t* dbg_prefix) {
   int rc = init_kernels();
@@ -275,36 +315,13 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
   if (p.direct) {
     LaunchTimer timer(kKDirect, stream);
     hipLaunchKernelGGL(k_direct<kDirectBlock>, dim3(1), dim3(kDirectBlock), p.slice_lds, stream, keys, n,
-                       range, p.sb, p.stage_cap, out, status, mode, dbg_bitmap, dbg_prefix);
+                       range, p.sb, p.stage_cap, out, status, mode, dbg_bitmap, dbg_prefix, p.bias);
     return launch_status();
   }
   uint32_t* table = reinterpret_cast<uint32_t*>(base + p.off_table);
   uint32_t* staging = reinterpret_cast<uint32_t*>(base + p.off_staging);
   uint64_t* info = reinterpret_cast<uint64_t*>(base + p.off_binfo);
-  const int vec_ok = (reinterpret_cast<uintptr_t>(keys) % 16u) == 0 ? 1 : 0;
-  const size_t part_lds = 4ull * (32 + round_up4(p.nb) + p.tile_keys);
-  {
-    LaunchTimer timer(kKPartition, stream);
-    switch (p.tile_log2) {
-      case 12:
-        hipLaunchKernelGGL((k_partition<256, 16>), dim3(p.nt), dim3(256), part_lds, stream, keys, n, range,
-                           p.sb, p.nb, staging, table, vec_ok);
-        break;
-      case 13:
-        hipLaunchKernelGGL((k_partition<512, 16>), dim3(p.nt), dim3(512), part_lds, stream, keys, n, range,
-                           p.sb, p.nb, staging, table, vec_ok);
-        break;
-      case 14:
-        hipLaunchKernelGGL((k_partition<1024, 16>), dim3(p.nt), dim3(1024), part_lds, stream, keys, n, range,
-                           p.sb, p.nb, staging, table, vec_ok);
-        break;
-      default:
-        hipLaunchKernelGGL((k_partition<1024, 32>), dim3(p.nt), dim3(1024), part_lds, stream, keys, n, range,
-                           p.sb, p.nb, staging, table, vec_ok);
-        break;
-    }
-    rc = launch_status();
-  }
+  rc = launch_partition(p, keys, n, staging, table, stream);
   if (rc != BITSORT_OK) return rc;
   uint32_t* bitvec = reinterpret_cast<uint32_t*>(base + p.off_bitvec);
   uint64_t* chunk_base = reinterpret_cast<uint64_t*>(base + p.off_chunk);
@@ -315,16 +332,60 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
     hipLaunchKernelGGL((k_slice<kSliceBlock, kSliceUnroll>), dim3(grid), dim3(kSliceBlock), p.slice_lds, stream,
                        staging, table, p.nt, p.tile_keys, p.sb, p.nb, p.stage_cap, out, info,
                        p.via_bitvec ? static_cast<int>(kToBitVector) : mode, dbg_bitmap, dbg_prefix, bitvec,
-                       chunk_base);
+                       chunk_base, 0u - p.bias);
     rc = launch_status();
   }
   if (rc != BITSORT_OK || mode == kDumpBitmap || (mode == kDumpPrefix && !p.via_bitvec)) return rc;
   if (p.via_bitvec) {
     LaunchTimer timer(kKEmit, stream);
     hipLaunchKernelGGL((k_emit<kEmitBlock>), dim3(static_cast<uint32_t>(p.n_chunks)), dim3(kEmitBlock), 0, stream,
-                       bitvec, chunk_base, out, mode, dbg_prefix);
+                       bitvec, chunk_base, out, mode, dbg_prefix, 0u - p.bias);
     rc = launch_status();
     if (rc != BITSORT_OK || mode != kEmit) return rc;
+  }
+  LaunchTimer timer(kKFinish, stream);
+  hipLaunchKernelGGL((k_finish<kSliceBlock>), dim3(1), dim3(kSliceBlock), 0, stream, n, p.nb, info, status, out);
+  return launch_status();
+}
+
+// ---- multiset (counting) sort --------------------------------------------------
+
+// Slices of 2^sb counters (10 <= sb <= 15) and at most 2^12 of them, so
+// range_bits <= 27; tiles as for the bitmap.
+void make_count_plan(uint64_t n, uint32_t rb, Plan* p) {
+  *p = Plan();
+  p->rb = rb;
+  p->direct = false;
+  uint32_t sb = rb > 8 ? rb - 8 : rb;
+  sb = std::max({sb, kCountMinSliceBits, rb > kMaxBucketsLog2 ? rb - kMaxBucketsLog2 : 0u});
+  sb = std::min(sb, kCountMaxSliceBits);
+  p->sb = sb;
+  p->nb = rb > sb ? 1u << (rb - sb) : 1u;
+  p->tile_log2 = n >= (1ull << 22) ? 14 : 12;
+  p->tile_keys = 1u << p->tile_log2;
+  p->nt = static_cast<uint32_t>((n + p->tile_keys - 1) >> p->tile_log2);
+  p->off_binfo = kHeaderBytes;
+  p->off_table = align256(p->off_binfo + 24ull * p->nb);
+  p->off_staging = align256(p->off_table + 4ull * p->nt * (p->nb + 1));
+  p->bytes = align256(p->off_staging + 4ull * p->nt * p->tile_keys);
+  p->slice_lds = 4ull * (64 + (kSliceBlock / kWave) * kWave + (1u << sb));
+}
+
+int run_count(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, void* ws, hipStream_t stream) {
+  int rc = init_kernels();
+  if (rc != BITSORT_OK) return rc;
+  char* base = static_cast<char*>(ws);
+  Status* status = reinterpret_cast<Status*>(base);
+  uint32_t* table = reinterpret_cast<uint32_t*>(base + p.off_table);
+  uint32_t* staging = reinterpret_cast<uint32_t*>(base + p.off_staging);
+  uint64_t* info = reinterpret_cast<uint64_t*>(base + p.off_binfo);
+  if ((rc = launch_partition(p, keys, n, staging, table, stream)) != BITSORT_OK) return rc;
+  {
+    LaunchTimer timer(kKCountSlice, stream);
+    const uint32_t grid = 8u * ((p.nb + 7u) / 8u);
+    hipLaunchKernelGGL((k_count_slice<kSliceBlock, kSliceUnroll>), dim3(grid), dim3(kSliceBlock), p.slice_lds,
+                       stream, staging, table, p.nt, p.tile_keys, p.sb, p.nb, out, info);
+    if ((rc = launch_status()) != BITSORT_OK) return rc;
   }
   LaunchTimer timer(kKFinish, stream);
   hipLaunchKernelGGL((k_finish<kSliceBlock>), dim3(1), dim3(kSliceBlock), 0, stream, n, p.nb, info, status, out);
@@ -415,6 +476,110 @@ int run_batch(const uint32_t* keys, const uint64_t* offsets, uint32_t num_segmen
 }
 
 // Library-owned workspaces, one per (device, stream).
+// ---- radix sort (the paper's Algorithm 1 in 8-bit digits) -------------------
+
+constexpr uint32_t kRadixItems = 32;
+constexpr uint64_t kRadixTileKeys = static_cast<uint64_t>(kRadixBlock) * kRadixItems;
+
+struct RadixPlan {
+  uint32_t passes = 0, hist_blocks = 1;
+  uint64_t ntiles = 0, clear_words = 0;
+  size_t off_tickets = 0, off_lookback = 0, off_partials = 0, off_digit = 0, off_tmp = 0, bytes = 0;
+};
+
+// Workspace: status header, then (cleared by k_radix_hist) one ticket per
+// pass and the look-back words [passes][tiles][256], then the partial
+// histograms, the digit starts, and a ping-pong buffer of n keys.
+void make_radix_plan(uint64_t n, uint32_t key_bits, RadixPlan* p) {
+  p->passes = (key_bits + 7u) / 8u;
+  p->ntiles = (n + kRadixTileKeys - 1) / kRadixTileKeys;
+  p->hist_blocks = static_cast<uint32_t>(
+      std::min<uint64_t>(kRadixHistBlocks, std::max<uint64_t>(1, (n + 1024ull * 64 - 1) / (1024ull * 64))));
+  size_t o = kHeaderBytes;
+  p->off_tickets = o;
+  o = align256(o + 4ull * kRadixMaxPasses);
+  p->off_lookback = o;
+  o = align256(o + 4ull * p->passes * p->ntiles * kRadixDigits);
+  p->clear_words = (o - p->off_tickets) / 4;
+  p->off_partials = o;
+  o = align256(o + 4ull * p->hist_blocks * kRadixPartStride);
+  p->off_digit = o;
+  o = align256(o + 4ull * kRadixMaxPasses * kRadixDigits);
+  p->off_tmp = o;
+  o = align256(o + 4ull * n);
+  p->bytes = o;
+}
+
+int check_radix_args(const uint32_t* keys, uint64_t n, uint32_t key_bits, const uint32_t* out) {
+  if (key_bits > 32) return BITSORT_ERR_INVALID_ARG;
+  if (n > 0 && (keys == nullptr || out == nullptr)) return BITSORT_ERR_INVALID_ARG;
+  if (n > kRadixMaxN) return BITSORT_ERR_TOO_LARGE;
+  if (n > 0 && keys != out) {
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(keys), a1 = a0 + 4 * n;
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(out), b1 = b0 + 4 * n;
+    if (a0 < b1 && b0 < a1) return BITSORT_ERR_INVALID_ARG;
+  }
+  return BITSORT_OK;
+}
+
+// Enqueue the radix sort: histogram + scan, then one launch per pass reading
+// from the previous pass's buffer.  The buffers alternate between `out` and
+// the workspace's tmp so that the last pass writes `out`; when out aliases
+// keys, pass 0 writes tmp and an odd pass count ends with a copy to out.
+int run_radix(const RadixPlan& p, const uint32_t* keys, uint64_t n, uint32_t key_bits, uint32_t flip, uint32_t* out,
+              void* ws, hipStream_t stream) {
+  char* base = static_cast<char*>(ws);
+  Status* status = reinterpret_cast<Status*>(base);
+  uint32_t* tickets = reinterpret_cast<uint32_t*>(base + p.off_tickets);
+  uint32_t* lookback = reinterpret_cast<uint32_t*>(base + p.off_lookback);
+  uint32_t* partials = reinterpret_cast<uint32_t*>(base + p.off_partials);
+  uint32_t* digit = reinterpret_cast<uint32_t*>(base + p.off_digit);
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(base + p.off_tmp);
+  int rc;
+  {
+    LaunchTimer timer(kKRadixHist, stream);
+    hipLaunchKernelGGL(k_radix_hist, dim3(p.hist_blocks), dim3(kRadixHistBlock), 0, stream, keys, n, key_bits, p.passes,
+                       flip, partials, reinterpret_cast<uint32_t*>(base + p.off_tickets), p.clear_words);
+    if ((rc = launch_status()) != BITSORT_OK) return rc;
+  }
+  {
+    LaunchTimer timer(kKRadixScan, stream);
+    hipLaunchKernelGGL(k_radix_scan, dim3(std::max(p.passes, 1u)), dim3(kRadixHistBlock), 0, stream, partials,
+                       p.hist_blocks, p.passes, n, digit, status);
+    if ((rc = launch_status()) != BITSORT_OK) return rc;
+  }
+  const bool alias = keys == out;
+  if (p.passes == 0) {
+    if (alias) return BITSORT_OK;
+    return hipMemcpyAsync(out, keys, 4 * n, hipMemcpyDeviceToDevice, stream) == hipSuccess ? BITSORT_OK
+                                                                                           : BITSORT_ERR_HIP;
+  }
+  uint32_t* bufs[2];
+  if (alias || p.passes % 2 == 0) {
+    bufs[0] = tmp;
+    bufs[1] = out;
+  } else {
+    bufs[0] = out;
+    bufs[1] = tmp;
+  }
+  const uint32_t* src = keys;
+  for (uint32_t pass = 0; pass < p.passes; ++pass) {
+    uint32_t* dst = bufs[pass % 2];
+    const uint32_t left = key_bits - 8 * pass;
+    const uint32_t dmask = left >= 8 ? 0xFFu : ((1u << left) - 1u);
+    LaunchTimer timer(kKRadixPass, stream);
+    hipLaunchKernelGGL((k_radix_pass<kRadixItems>), dim3(static_cast<uint32_t>(p.ntiles)), dim3(kRadixBlock), 0,
+                       stream, src, dst, n, 8 * pass, dmask, flip, digit + pass * kRadixDigits,
+                       lookback + static_cast<uint64_t>(pass) * p.ntiles * kRadixDigits, tickets + pass, status);
+    if ((rc = launch_status()) != BITSORT_OK) return rc;
+    src = dst;
+  }
+  if (src != out &&
+      hipMemcpyAsync(out, src, 4 * n, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+    return BITSORT_ERR_HIP;
+  return BITSORT_OK;
+}
+
 struct StreamCtx {
   void* ws = nullptr;
   size_t bytes = 0;
@@ -471,6 +636,27 @@ void splitmix_keys(uint64_t seed, uint32_t k[4]) {
     z ^= z >> 31;
     k[i] = static_cast<uint32_t>(z);
   }
+}
+
+int radix_on_stream(const uint32_t* keys, uint64_t n, uint32_t key_bits, uint32_t flip, uint32_t* out,
+                           bitsort_stream_t stream) {
+  int rc = check_radix_args(keys, n, key_bits, out);
+  if (rc != BITSORT_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  StreamCtx& c = ctx_for(stream);
+  c.used = true;
+  if (n == 0) {
+    c.last_empty = true;
+    return BITSORT_OK;
+  }
+  if ((rc = init_kernels()) != BITSORT_OK) return rc;
+  RadixPlan p;
+  make_radix_plan(n, key_bits, &p);
+  rc = grow(&c.ws, &c.bytes, p.bytes, s);
+  if (rc != BITSORT_OK) return rc;
+  c.last_empty = false;
+  return run_radix(p, keys, n, key_bits, flip, out, c.ws, s);
 }
 
 #include "serve.inc"
@@ -530,6 +716,83 @@ int bitsort_u32(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32_t*
   }
   Plan p;
   make_plan(n, range_bits, &p);
+  rc = grow(&c.ws, &c.bytes, p.bytes, s);
+  if (rc != BITSORT_OK) return rc;
+  c.last_empty = false;
+  return run_plain(p, keys, n, out, c.ws, s, kEmit, nullptr, nullptr);
+}
+
+size_t bitsort_radix_workspace_bytes(uint64_t n, uint32_t key_bits) {
+  if (key_bits > 32 || n > kRadixMaxN) return 0;
+  RadixPlan p;
+  make_radix_plan(n, key_bits, &p);
+  return p.bytes;
+}
+
+int bitsort_radix_u32_ws(const uint32_t* keys, uint64_t n, uint32_t key_bits, uint32_t* out, void* workspace,
+                         size_t ws_bytes, bitsort_stream_t stream) {
+  int rc = check_radix_args(keys, n, key_bits, out);
+  if (rc != BITSORT_OK) return rc;
+  if (workspace == nullptr || (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return BITSORT_ERR_INVALID_ARG;
+  RadixPlan p;
+  make_radix_plan(n, key_bits, &p);
+  if (ws_bytes < p.bytes) return BITSORT_ERR_NO_MEMORY;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n == 0) return hipMemsetAsync(workspace, 0, sizeof(Status), s) == hipSuccess ? BITSORT_OK : BITSORT_ERR_HIP;
+  if ((rc = init_kernels()) != BITSORT_OK) return rc;
+  return run_radix(p, keys, n, key_bits, 0u, out, workspace, s);
+}
+
+int bitsort_count_u32(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32_t* out, bitsort_stream_t stream) {
+  if (range_bits > kCountMaxRangeBits) return BITSORT_ERR_INVALID_ARG;
+  if (n > 0 && (keys == nullptr || out == nullptr)) return BITSORT_ERR_INVALID_ARG;
+  if (n >= (1ull << 32)) return BITSORT_ERR_TOO_LARGE;
+  if (n > 0 && keys != out) {
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(keys), a1 = a0 + 4 * n;
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(out), b1 = b0 + 4 * n;
+    if (a0 < b1 && b0 < a1) return BITSORT_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  StreamCtx& c = ctx_for(stream);
+  c.used = true;
+  if (n == 0) {
+    c.last_empty = true;
+    return BITSORT_OK;
+  }
+  Plan p;
+  make_count_plan(n, range_bits, &p);
+  int rc = grow(&c.ws, &c.bytes, p.bytes, s);
+  if (rc != BITSORT_OK) return rc;
+  c.last_empty = false;
+  return run_count(p, keys, n, out, c.ws, s);
+}
+
+int bitsort_radix_u32(const uint32_t* keys, uint64_t n, uint32_t key_bits, uint32_t* out, bitsort_stream_t stream) {
+  return radix_on_stream(keys, n, key_bits, 0u, out, stream);
+}
+
+int bitsort_radix_i32(const int32_t* keys, uint64_t n, int32_t* out, bitsort_stream_t stream) {
+  return radix_on_stream(reinterpret_cast<const uint32_t*>(keys), n, 32, 0x80000000u, reinterpret_cast<uint32_t*>(out),
+                         stream);
+}
+
+int bitsort_i32(const int32_t* keys_s, uint64_t n, uint32_t range_bits, int32_t* out_s, bitsort_stream_t stream) {
+  const uint32_t* keys = reinterpret_cast<const uint32_t*>(keys_s);
+  uint32_t* out = reinterpret_cast<uint32_t*>(out_s);
+  int rc = check_args(keys, n, range_bits, out);
+  if (rc != BITSORT_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  StreamCtx& c = ctx_for(stream);
+  c.used = true;
+  if (n == 0) {
+    c.last_empty = true;
+    return BITSORT_OK;
+  }
+  Plan p;
+  make_plan(n, range_bits, &p);
+  p.bias = range_bits ? (1u << (range_bits - 1)) : 0u;
   rc = grow(&c.ws, &c.bytes, p.bytes, s);
   if (rc != BITSORT_OK) return rc;
   c.last_empty = false;

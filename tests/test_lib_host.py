@@ -43,6 +43,16 @@ def test_host_argument_checks(lib):
     assert E.bitsort_set_tuning(0, 0, 3) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_batch_u32(fake, fake, 0, fake, fake, 0, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_generate_u32(fake, 10, 1, 3, 0, 0) == E.BITSORT_ERR_TOO_LARGE
+    assert E.bitsort_radix_u32(fake, 10, 33, fake + 4096, 0) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_radix_u32(0, 10, 32, fake, 0) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_radix_u32(fake, 1 << 30, 32, fake + (1 << 34), 0) == E.BITSORT_ERR_TOO_LARGE
+    assert E.bitsort_radix_u32(fake, 100, 32, fake + 4, 0) == E.BITSORT_ERR_INVALID_ARG  # partial overlap
+    assert E.bitsort_radix_workspace_bytes(10, 33) == 0
+    assert E.bitsort_count_u32(fake, 10, 28, fake + 4096, 0) == E.BITSORT_ERR_INVALID_ARG  # range_bits > 27
+    assert E.bitsort_count_u32(fake, 100, 20, fake + 4, 0) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_i32(fake, 10, 33, fake + 4096, 0) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_radix_i32(fake, 100, fake + 4, 0) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_radix_u32_ws(fake, 10, 32, fake + 4096, fake, 16, 0) == E.BITSORT_ERR_NO_MEMORY
 
 
 def test_plan_shapes(lib):
@@ -54,6 +64,11 @@ def test_plan_shapes(lib):
     assert rc == 0 and nb == 1 and tl == 0 and ep == 0  # single-workgroup path
     ws = _lib.bitsort_workspace_bytes(1 << 26, 28)
     assert ws >= 4 * (1 << 26)
+    # radix: a ping-pong buffer of n keys plus the same look-back state per pass
+    n = 1 << 24
+    r = [_lib.bitsort_radix_workspace_bytes(n, kb) for kb in (8, 16, 24, 32)]
+    assert r[0] >= 4 * n
+    assert r[1] - r[0] == r[2] - r[1] == r[3] - r[2] > 0
 
 
 def test_single_hip_runtime_whatever_the_import_order():
