@@ -62,6 +62,8 @@ class Oracle:
             "oracle_bitmap_sort_segments_u32": (
                 c.c_int, [_u32p, _u64p, c.c_uint32, _u8p, _u32p, _u64p, _u32p]),
             "oracle_bitwise_sort1_u32": (c.c_int, [_u32p, c.c_uint64, c.c_uint32]),
+            "oracle_bitwise_sort1_u64": (c.c_int, [_u64p, c.c_uint64, c.c_uint32]),
+            "oracle_bitwise_sort1_pairs_u32": (c.c_int, [_u32p, _u32p, c.c_uint64, c.c_uint32]),
             "oracle_bitwise_sort_i32": (c.c_int, [_i32p, c.c_uint64]),
             "oracle_counting_sort_u32": (c.c_int, [_u32p, c.c_uint64, c.c_uint32, _u32p, _u64p, _u32p]),
             "oracle_bitmap_sort_u64": (c.c_int, [_u64p, c.c_uint64, c.c_uint32, _u64p, _u64p, _u32p]),
@@ -198,6 +200,29 @@ class Oracle:
         if rc != 0:
             raise OracleError(f"oracle_bitwise_sort1_u32 -> {rc}")
         return a
+
+    def bitwise_sort1_u64(self, keys, passes: int = 64) -> np.ndarray:
+        """BitwiseSort1 for T = uint64 (a sorted copy)."""
+        a = np.array(keys, dtype=np.uint64, copy=True)
+        if a.size == 0:
+            return a
+        rc = self._lib.oracle_bitwise_sort1_u64(_ptr(a, _u64p), a.size, passes)
+        if rc != 0:
+            raise OracleError(f"oracle_bitwise_sort1_u64 -> {rc}")
+        return a
+
+    def bitwise_sort1_pairs(self, keys, values, passes: int = 32):
+        """BitwiseSort1 on (key, value) records: (sorted keys, their values)."""
+        k = np.array(keys, dtype=np.uint32, copy=True)
+        v = np.array(values, dtype=np.uint32, copy=True)
+        if k.size != v.size:
+            raise ValueError("keys and values differ in length")
+        if k.size == 0:
+            return k, v
+        rc = self._lib.oracle_bitwise_sort1_pairs_u32(_ptr(k, _u32p), _ptr(v, _u32p), k.size, passes)
+        if rc != 0:
+            raise OracleError(f"oracle_bitwise_sort1_pairs_u32 -> {rc}")
+        return k, v
 
     def bitwise_sort_i32(self, keys) -> np.ndarray:
         """The paper's BitwiseSort (sign split) on int32 (a sorted copy)."""

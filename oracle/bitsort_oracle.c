@@ -301,6 +301,87 @@ int oracle_bitwise_sort1_u32(uint32_t *A, uint64_t n, uint32_t passes)
     return ORACLE_OK;
 }
 
+/* BitwiseSort1 for T = uint64 (t = 64 bits): the same stable partition by
+ * bit k, for k = 0 .. passes-1, passes <= 64. */
+int oracle_bitwise_sort1_u64(uint64_t *A, uint64_t n, uint32_t passes)
+{
+    if (passes > 64 || (n > 0 && A == NULL))
+        return ORACLE_ERR_ARG;
+    if (n == 0)
+        return ORACLE_OK;
+    uint64_t *A0 = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    uint64_t *A1 = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    if (A0 == NULL || A1 == NULL) {
+        free(A0);
+        free(A1);
+        return ORACLE_ERR_NOMEM;
+    }
+    for (uint32_t k = 0; k < passes; k++) {
+        const uint64_t bit = (uint64_t)1 << k;
+        uint64_t n0 = 0, n1 = 0;
+        for (uint64_t i = 0; i < n; i++) {
+            if (A[i] & bit)
+                A1[n1++] = A[i];
+            else
+                A0[n0++] = A[i];
+        }
+        for (uint64_t i = 0; i < n0; i++)
+            A[i] = A0[i];
+        for (uint64_t i = 0; i < n1; i++)
+            A[n0 + i] = A1[i];
+    }
+    free(A0);
+    free(A1);
+    return ORACLE_OK;
+}
+
+/* BitwiseSort1 on records (K[i], V[i]): the bit test reads the key, and the
+ * partition moves the whole record, so each value travels with its key and
+ * records with equal keys keep their input order. */
+int oracle_bitwise_sort1_pairs_u32(uint32_t *K, uint32_t *V, uint64_t n, uint32_t passes)
+{
+    if (passes > 32 || (n > 0 && (K == NULL || V == NULL)))
+        return ORACLE_ERR_ARG;
+    if (n == 0)
+        return ORACLE_OK;
+    uint32_t *K0 = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    uint32_t *K1 = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    uint32_t *V0 = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    uint32_t *V1 = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    if (K0 == NULL || K1 == NULL || V0 == NULL || V1 == NULL) {
+        free(K0);
+        free(K1);
+        free(V0);
+        free(V1);
+        return ORACLE_ERR_NOMEM;
+    }
+    for (uint32_t k = 0; k < passes; k++) {
+        uint64_t n0 = 0, n1 = 0;
+        for (uint64_t i = 0; i < n; i++) {
+            if (K[i] & (1u << k)) {
+                K1[n1] = K[i];
+                V1[n1++] = V[i];
+            } else {
+                K0[n0] = K[i];
+                V0[n0++] = V[i];
+            }
+        }
+        for (uint64_t i = 0; i < n0; i++) {
+            K[i] = K0[i];
+            V[i] = V0[i];
+        }
+        for (uint64_t i = 0; i < n1; i++) {
+            K[n0 + i] = K1[i];
+            V[n0 + i] = V1[i];
+        }
+    }
+    free(K0);
+    free(K1);
+    free(V0);
+    free(V1);
+    return ORACLE_OK;
+}
+
 /* BitwiseSort on signed 32-bit keys: negatives and non-negatives are split
  * apart, each part is sorted by BitwiseSort1 over the t-1 = 31 bits below the
  * sign bit (all its elements share the sign bit), and the negatives are put

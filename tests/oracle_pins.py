@@ -229,6 +229,40 @@ def pin_signed(o):
     assert o.bitwise_sort_i32(np.array([3, -2, 0], dtype=np.int32)).tolist() == [-2, 0, 3]
 
 
+def pin_algorithm1_u64(o):
+    """Algorithm 1 for T = uint64: 64 passes equal numpy's sort (keys above
+    2^32 and 2^63 included), and Theorem 1's induction holds at every pass
+    count (Python's stable sort by the low p bits is the reference)."""
+    rng = np.random.default_rng(47)
+    keys = rng.integers(0, 1 << 64, size=3000, dtype=np.uint64)
+    keys[:4] = [0, (1 << 64) - 1, 1 << 63, (1 << 32) + 1]
+    assert np.array_equal(o.bitwise_sort1_u64(keys, 64), np.sort(keys))
+    small = [int(v) for v in keys[:400]] + [7, 7 + (1 << 40), 7 + (1 << 63)]
+    for p in (0, 1, 8, 32, 33, 40, 63, 64):
+        mask = (1 << p) - 1
+        expect = sorted(small, key=lambda v: v & mask)
+        assert o.bitwise_sort1_u64(np.array(small, dtype=np.uint64), p).tolist() == expect, p
+
+
+def pin_pairs(o):
+    """Algorithm 1 on (key, value) records: the keys come out sorted and the
+    values follow their keys in input order among equal keys -- numpy's
+    stable argsort of the keys; after p passes, Python's stable sort by the
+    low p bits."""
+    rng = np.random.default_rng(53)
+    keys = rng.integers(0, 300, size=5000, dtype=np.uint64).astype(np.uint32)
+    keys[::7] = rng.integers(0, 1 << 32, size=keys[::7].size, dtype=np.uint64).astype(np.uint32)
+    vals = np.arange(keys.size, dtype=np.uint32)
+    k, v = o.bitwise_sort1_pairs(keys, vals, 32)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(k, keys[order]) and np.array_equal(v, vals[order])
+    for p in (0, 3, 9, 31):
+        mask = (1 << p) - 1
+        idx = sorted(range(600), key=lambda i: int(keys[i]) & mask)
+        k, v = o.bitwise_sort1_pairs(keys[:600], vals[:600], p)
+        assert v.tolist() == idx and k.tolist() == [int(keys[i]) for i in idx], p
+
+
 # ---- precondition violations and edges --------------------------------------------------
 
 def pin_duplicates(o):
@@ -319,7 +353,7 @@ ALL_PINS = [
     pin_table1, pin_table2, pin_helpers, pin_all_subsets, pin_random_tiny,
     pin_permutation_identity, pin_invariants, pin_word_width, pin_scan, pin_mark_emit,
     pin_algorithm1, pin_theorem1, pin_signed, pin_duplicates, pin_out_of_range, pin_edges,
-    pin_segments, pin_counting, pin_u64,
+    pin_segments, pin_counting, pin_u64, pin_algorithm1_u64, pin_pairs,
 ]
 
 
