@@ -217,6 +217,27 @@ int bitsort_count_u32(const uint32_t *keys, uint64_t n, uint32_t range_bits, uin
 int bitsort_radix_i32(const int32_t *keys, uint64_t n, int32_t *out, bitsort_stream_t stream);
 
 /*
+ * The radix sort for T = uint64 (Algorithm 1 is written for any integer type
+ * T with 8 * sizeof(T) bit passes): keys ordered by their low key_bits bits
+ * (0..64), ceil(key_bits / 8) passes, duplicates kept.  keys/out are device
+ * pointers to n uint64; everything else as bitsort_radix_u32 (status on the
+ * stream, out == keys allowed, n < 2^30).
+ */
+int bitsort_radix_u64(const uint64_t *keys, uint64_t n, uint32_t key_bits, uint64_t *out, bitsort_stream_t stream);
+
+/*
+ * Key-value radix sort: records (keys[i], values[i]) ordered by the low
+ * key_bits bits of the key, stably -- the partition of Algorithm 1 moves the
+ * whole record, so each value travels with its key and records with equal
+ * keys keep their input order.  All four arrays are device pointers to n
+ * uint32.  out_keys == keys and out_values == values are allowed; any other
+ * overlap among the outputs and between an output and an input is rejected.
+ * Otherwise as bitsort_radix_u32.
+ */
+int bitsort_radix_pairs_u32(const uint32_t *keys, const uint32_t *values, uint64_t n, uint32_t key_bits,
+                            uint32_t *out_keys, uint32_t *out_values, bitsort_stream_t stream);
+
+/*
  * Device-side input generator (the synthetic workloads): out[i] = pi(first + i)
  * for i < count, where pi is the seeded keyed permutation of [0, 2^range_bits)
  * (4-round alternating Feistel network over halves of ceil(range_bits/2) and

@@ -17,7 +17,8 @@ __all__ = [
     "debug_prefix", "workspace_bytes", "sort_ws", "workspace_status", "set_tuning",
     "plan_info", "BitsortError", "Status", "STATUS_OUT_OF_RANGE", "STATUS_DUPLICATE",
     "STATUS_BAD_SEGMENT", "Graph", "autotune", "autotune_batch", "tuning_save", "tuning_load",
-    "tuning_clear", "radix_sort", "radix_workspace_bytes", "radix_sort_ws", "STATUS_TIMEOUT", "sort_signed", "radix_sort_signed", "sort_multiset",
+    "tuning_clear", "radix_sort", "radix_workspace_bytes", "radix_sort_ws", "STATUS_TIMEOUT", "sort_signed", "radix_sort_signed", "sort_multiset", "radix_sort_u64",
+    "radix_sort_pairs",
 ]
 
 
@@ -119,6 +120,40 @@ def sort_multiset(keys, range_bits: int, out=None, stream=None):
     _lib.check(_lib.bitsort_count_u32(keys.data_ptr(), keys.numel(), range_bits, out.data_ptr(), _stream(stream)),
                "bitsort_count_u32")
     return out
+
+
+def radix_sort_u64(keys, key_bits: int = 64, out=None, stream=None):
+    """Stable LSD radix sort of 64-bit keys (int64/uint64 tensor read as
+    uint64) by their low ``key_bits`` bits; duplicates kept."""
+    torch = _torch()
+    if not keys.is_cuda or keys.dtype not in (torch.int64, torch.uint64) or not keys.is_contiguous():
+        raise TypeError("keys must be a contiguous 64-bit device tensor")
+    if out is None:
+        out = torch.empty_like(keys)
+    if out.dtype != keys.dtype or out.numel() != keys.numel() or not out.is_contiguous():
+        raise ValueError("out must match keys")
+    _lib.check(_lib.bitsort_radix_u64(keys.data_ptr(), keys.numel(), key_bits, out.data_ptr(), _stream(stream)),
+               "bitsort_radix_u64")
+    return out
+
+
+def radix_sort_pairs(keys, values, key_bits: int = 32, out_keys=None, out_values=None, stream=None):
+    """Stable key-value LSD radix sort of 32-bit keys with 32-bit values."""
+    torch = _torch()
+    _check_u32(keys, "keys")
+    _check_u32(values, "values")
+    if values.numel() != keys.numel():
+        raise ValueError("keys and values differ in length")
+    if out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if out_values is None:
+        out_values = torch.empty_like(values)
+    _check_u32(out_keys, "out_keys")
+    _check_u32(out_values, "out_values")
+    _lib.check(_lib.bitsort_radix_pairs_u32(keys.data_ptr(), values.data_ptr(), keys.numel(), key_bits,
+                                            out_keys.data_ptr(), out_values.data_ptr(), _stream(stream)),
+               "bitsort_radix_pairs_u32")
+    return out_keys, out_values
 
 
 def radix_workspace_bytes(n: int, key_bits: int = 32) -> int:

@@ -58,6 +58,8 @@ _SIGS = {
     "bitsort_u32_ws": (_c.c_int, [_vp, _u64, _u32, _vp, _vp, _c.c_size_t, _vp]),
     "bitsort_radix_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
     "bitsort_radix_i32": (_c.c_int, [_vp, _u64, _vp, _vp]),
+    "bitsort_radix_u64": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
+    "bitsort_radix_pairs_u32": (_c.c_int, [_vp, _vp, _u64, _u32, _vp, _vp, _vp]),
     "bitsort_i32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
     "bitsort_count_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
     "bitsort_radix_workspace_bytes": (_c.c_size_t, [_u64, _u32]),
@@ -157,6 +159,15 @@ def bitsort_radix_u32(keys: int, n: int, key_bits: int, out: int, stream: int) -
 
 def bitsort_radix_i32(keys: int, n: int, out: int, stream: int) -> int:
     return lib().bitsort_radix_i32(keys, n, out, stream)
+
+
+def bitsort_radix_u64(keys: int, n: int, key_bits: int, out: int, stream: int) -> int:
+    return lib().bitsort_radix_u64(keys, n, key_bits, out, stream)
+
+
+def bitsort_radix_pairs_u32(keys: int, values: int, n: int, key_bits: int, out_keys: int, out_values: int,
+                            stream: int) -> int:
+    return lib().bitsort_radix_pairs_u32(keys, values, n, key_bits, out_keys, out_values, stream)
 
 
 def bitsort_count_u32(keys: int, n: int, range_bits: int, out: int, stream: int) -> int:

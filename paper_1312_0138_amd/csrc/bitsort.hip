@@ -478,104 +478,129 @@ int run_batch(const uint32_t* keys, const uint64_t* offsets, uint32_t num_segmen
 // Library-owned workspaces, one per (device, stream).
 // ---- radix sort (the paper's Algorithm 1 in 8-bit digits) -------------------
 
-constexpr uint32_t kRadixItems = 32;
-constexpr uint64_t kRadixTileKeys = static_cast<uint64_t>(kRadixBlock) * kRadixItems;
-
 struct RadixPlan {
-  uint32_t passes = 0, hist_blocks = 1;
+  uint32_t passes = 0, hist_blocks = 1, key_bytes = 4, items = 32;
+  bool pairs = false;
   uint64_t ntiles = 0, clear_words = 0;
-  size_t off_tickets = 0, off_lookback = 0, off_partials = 0, off_digit = 0, off_tmp = 0, bytes = 0;
+  size_t off_tickets = 0, off_lookback = 0, off_partials = 0, off_digit = 0, off_tmp = 0, off_vtmp = 0, bytes = 0;
 };
+
+// Items per thread of k_radix_pass: 32 for 32-bit keys alone, 16 when the
+// tile's LDS holds 8-byte keys or keys and values (32 KiB either way).
+constexpr uint32_t radix_items(uint32_t key_bytes, bool pairs) { return key_bytes == 4 && !pairs ? 32u : 16u; }
 
 // Workspace: status header, then (cleared by k_radix_hist) one ticket per
 // pass and the look-back words [passes][tiles][256], then the partial
-// histograms, the digit starts, and a ping-pong buffer of n keys.
-void make_radix_plan(uint64_t n, uint32_t key_bits, RadixPlan* p) {
+// histograms, the digit starts, and ping-pong buffers of n keys (and values).
+void make_radix_plan(uint64_t n, uint32_t key_bits, uint32_t key_bytes, bool pairs, RadixPlan* p) {
   p->passes = (key_bits + 7u) / 8u;
-  p->ntiles = (n + kRadixTileKeys - 1) / kRadixTileKeys;
+  p->key_bytes = key_bytes;
+  p->pairs = pairs;
+  p->items = radix_items(key_bytes, pairs);
+  const uint64_t tile = static_cast<uint64_t>(kRadixBlock) * p->items;
+  p->ntiles = (n + tile - 1) / tile;
   p->hist_blocks = static_cast<uint32_t>(
       std::min<uint64_t>(kRadixHistBlocks, std::max<uint64_t>(1, (n + 1024ull * 64 - 1) / (1024ull * 64))));
+  const uint32_t stride = key_bytes == 8 ? RadixTraits<uint64_t>::kPartStride : RadixTraits<uint32_t>::kPartStride;
   size_t o = kHeaderBytes;
   p->off_tickets = o;
-  o = align256(o + 4ull * kRadixMaxPasses);
+  o = align256(o + 4ull * kRadixMaxPassesAll);
   p->off_lookback = o;
   o = align256(o + 4ull * p->passes * p->ntiles * kRadixDigits);
   p->clear_words = (o - p->off_tickets) / 4;
   p->off_partials = o;
-  o = align256(o + 4ull * p->hist_blocks * kRadixPartStride);
+  o = align256(o + 4ull * p->hist_blocks * stride);
   p->off_digit = o;
-  o = align256(o + 4ull * kRadixMaxPasses * kRadixDigits);
+  o = align256(o + 4ull * kRadixMaxPassesAll * kRadixDigits);
   p->off_tmp = o;
-  o = align256(o + 4ull * n);
+  o = align256(o + key_bytes * n);
+  p->off_vtmp = o;
+  if (pairs) o = align256(o + 4ull * n);
   p->bytes = o;
 }
 
-int check_radix_args(const uint32_t* keys, uint64_t n, uint32_t key_bits, const uint32_t* out) {
-  if (key_bits > 32) return BITSORT_ERR_INVALID_ARG;
+bool overlaps(const void* a, const void* b, uint64_t bytes) {
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+  return a0 < b0 + bytes && b0 < a0 + bytes;
+}
+
+int check_radix_args(const void* keys, uint64_t n, uint32_t key_bits, uint32_t key_bytes, const void* out) {
+  if (key_bits > 8 * key_bytes) return BITSORT_ERR_INVALID_ARG;
   if (n > 0 && (keys == nullptr || out == nullptr)) return BITSORT_ERR_INVALID_ARG;
   if (n > kRadixMaxN) return BITSORT_ERR_TOO_LARGE;
-  if (n > 0 && keys != out) {
-    const uintptr_t a0 = reinterpret_cast<uintptr_t>(keys), a1 = a0 + 4 * n;
-    const uintptr_t b0 = reinterpret_cast<uintptr_t>(out), b1 = b0 + 4 * n;
-    if (a0 < b1 && b0 < a1) return BITSORT_ERR_INVALID_ARG;
-  }
+  if (n > 0 && keys != out && overlaps(keys, out, key_bytes * n)) return BITSORT_ERR_INVALID_ARG;
   return BITSORT_OK;
 }
 
 // Enqueue the radix sort: histogram + scan, then one launch per pass reading
 // from the previous pass's buffer.  The buffers alternate between `out` and
-// the workspace's tmp so that the last pass writes `out`; when out aliases
-// keys, pass 0 writes tmp and an odd pass count ends with a copy to out.
-int run_radix(const RadixPlan& p, const uint32_t* keys, uint64_t n, uint32_t key_bits, uint32_t flip, uint32_t* out,
-              void* ws, hipStream_t stream) {
+// the workspace's tmp so that the last pass writes `out`; when an output
+// aliases its input, pass 0 writes tmp and an odd pass count ends with a copy.
+template <typename K, bool PAIRS>
+int run_radix(const RadixPlan& p, const K* keys, const uint32_t* vals, uint64_t n, uint32_t key_bits, K flip, K* out,
+              uint32_t* vout, void* ws, hipStream_t stream) {
+  using T = RadixTraits<K>;
+  constexpr int kItems = static_cast<int>(radix_items(sizeof(K), PAIRS));
   char* base = static_cast<char*>(ws);
   Status* status = reinterpret_cast<Status*>(base);
   uint32_t* tickets = reinterpret_cast<uint32_t*>(base + p.off_tickets);
   uint32_t* lookback = reinterpret_cast<uint32_t*>(base + p.off_lookback);
   uint32_t* partials = reinterpret_cast<uint32_t*>(base + p.off_partials);
   uint32_t* digit = reinterpret_cast<uint32_t*>(base + p.off_digit);
-  uint32_t* tmp = reinterpret_cast<uint32_t*>(base + p.off_tmp);
+  K* tmp = reinterpret_cast<K*>(base + p.off_tmp);
+  uint32_t* vtmp = reinterpret_cast<uint32_t*>(base + p.off_vtmp);
   int rc;
   {
     LaunchTimer timer(kKRadixHist, stream);
-    hipLaunchKernelGGL(k_radix_hist, dim3(p.hist_blocks), dim3(kRadixHistBlock), 0, stream, keys, n, key_bits, p.passes,
-                       flip, partials, reinterpret_cast<uint32_t*>(base + p.off_tickets), p.clear_words);
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3(p.hist_blocks), dim3(kRadixHistBlock), 0, stream, keys, n, key_bits,
+                       p.passes, flip, partials, tickets, p.clear_words);
     if ((rc = launch_status()) != BITSORT_OK) return rc;
   }
   {
     LaunchTimer timer(kKRadixScan, stream);
     hipLaunchKernelGGL(k_radix_scan, dim3(std::max(p.passes, 1u)), dim3(kRadixHistBlock), 0, stream, partials,
-                       p.hist_blocks, p.passes, n, digit, status);
+                       p.hist_blocks, T::kPartStride, T::kMaxPasses * kRadixDigits, p.passes, n, digit, status);
     if ((rc = launch_status()) != BITSORT_OK) return rc;
   }
-  const bool alias = keys == out;
+  const bool alias = static_cast<const void*>(keys) == out || (PAIRS && static_cast<const void*>(vals) == vout);
   if (p.passes == 0) {
-    if (alias) return BITSORT_OK;
-    return hipMemcpyAsync(out, keys, 4 * n, hipMemcpyDeviceToDevice, stream) == hipSuccess ? BITSORT_OK
-                                                                                           : BITSORT_ERR_HIP;
+    if (static_cast<const void*>(keys) != out &&
+        hipMemcpyAsync(out, keys, sizeof(K) * n, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+      return BITSORT_ERR_HIP;
+    if (PAIRS && vals != vout && hipMemcpyAsync(vout, vals, 4 * n, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+      return BITSORT_ERR_HIP;
+    return BITSORT_OK;
   }
-  uint32_t* bufs[2];
+  K* bufs[2];
+  uint32_t* vbufs[2];
   if (alias || p.passes % 2 == 0) {
     bufs[0] = tmp;
     bufs[1] = out;
+    vbufs[0] = vtmp;
+    vbufs[1] = vout;
   } else {
     bufs[0] = out;
     bufs[1] = tmp;
+    vbufs[0] = vout;
+    vbufs[1] = vtmp;
   }
-  const uint32_t* src = keys;
+  const K* src = keys;
+  const uint32_t* vsrc = vals;
   for (uint32_t pass = 0; pass < p.passes; ++pass) {
-    uint32_t* dst = bufs[pass % 2];
-    const uint32_t left = key_bits - 8 * pass;
-    const uint32_t dmask = left >= 8 ? 0xFFu : ((1u << left) - 1u);
+    K* dst = bufs[pass % 2];
+    uint32_t* vdst = vbufs[pass % 2];
     LaunchTimer timer(kKRadixPass, stream);
-    hipLaunchKernelGGL((k_radix_pass<kRadixItems>), dim3(static_cast<uint32_t>(p.ntiles)), dim3(kRadixBlock), 0,
-                       stream, src, dst, n, 8 * pass, dmask, flip, digit + pass * kRadixDigits,
-                       lookback + static_cast<uint64_t>(pass) * p.ntiles * kRadixDigits, tickets + pass, status);
+    hipLaunchKernelGGL((k_radix_pass<K, PAIRS, kItems>), dim3(static_cast<uint32_t>(p.ntiles)), dim3(kRadixBlock), 0,
+                       stream, src, dst, vsrc, vdst, n, 8 * pass, radix_digit_mask(key_bits, pass), flip,
+                       digit + pass * kRadixDigits, lookback + static_cast<uint64_t>(pass) * p.ntiles * kRadixDigits,
+                       tickets + pass, status);
     if ((rc = launch_status()) != BITSORT_OK) return rc;
     src = dst;
+    vsrc = vdst;
   }
-  if (src != out &&
-      hipMemcpyAsync(out, src, 4 * n, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+  if (src != out && hipMemcpyAsync(out, src, sizeof(K) * n, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+    return BITSORT_ERR_HIP;
+  if (PAIRS && vsrc != vout && hipMemcpyAsync(vout, vsrc, 4 * n, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return BITSORT_ERR_HIP;
   return BITSORT_OK;
 }
@@ -638,10 +663,18 @@ void splitmix_keys(uint64_t seed, uint32_t k[4]) {
   }
 }
 
-int radix_on_stream(const uint32_t* keys, uint64_t n, uint32_t key_bits, uint32_t flip, uint32_t* out,
-                           bitsort_stream_t stream) {
-  int rc = check_radix_args(keys, n, key_bits, out);
+// Radix sort on the stream's library workspace (grown as needed).
+template <typename K, bool PAIRS>
+int radix_on_stream(const K* keys, const uint32_t* vals, uint64_t n, uint32_t key_bits, K flip, K* out, uint32_t* vout,
+                    bitsort_stream_t stream) {
+  int rc = check_radix_args(keys, n, key_bits, sizeof(K), out);
   if (rc != BITSORT_OK) return rc;
+  if (PAIRS && n > 0) {
+    if (vals == nullptr || vout == nullptr) return BITSORT_ERR_INVALID_ARG;
+    if (vals != vout && overlaps(vals, vout, 4 * n)) return BITSORT_ERR_INVALID_ARG;
+    if (overlaps(out, vout, 4 * n) || overlaps(keys, vout, 4 * n) || overlaps(vals, out, 4 * n))
+      return BITSORT_ERR_INVALID_ARG;
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lock(g_mu);
   StreamCtx& c = ctx_for(stream);
@@ -652,11 +685,11 @@ int radix_on_stream(const uint32_t* keys, uint64_t n, uint32_t key_bits, uint32_
   }
   if ((rc = init_kernels()) != BITSORT_OK) return rc;
   RadixPlan p;
-  make_radix_plan(n, key_bits, &p);
+  make_radix_plan(n, key_bits, sizeof(K), PAIRS, &p);
   rc = grow(&c.ws, &c.bytes, p.bytes, s);
   if (rc != BITSORT_OK) return rc;
   c.last_empty = false;
-  return run_radix(p, keys, n, key_bits, flip, out, c.ws, s);
+  return run_radix<K, PAIRS>(p, keys, vals, n, key_bits, flip, out, vout, c.ws, s);
 }
 
 #include "serve.inc"
@@ -725,22 +758,22 @@ int bitsort_u32(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32_t*
 size_t bitsort_radix_workspace_bytes(uint64_t n, uint32_t key_bits) {
   if (key_bits > 32 || n > kRadixMaxN) return 0;
   RadixPlan p;
-  make_radix_plan(n, key_bits, &p);
+  make_radix_plan(n, key_bits, 4, false, &p);
   return p.bytes;
 }
 
 int bitsort_radix_u32_ws(const uint32_t* keys, uint64_t n, uint32_t key_bits, uint32_t* out, void* workspace,
                          size_t ws_bytes, bitsort_stream_t stream) {
-  int rc = check_radix_args(keys, n, key_bits, out);
+  int rc = check_radix_args(keys, n, key_bits, 4, out);
   if (rc != BITSORT_OK) return rc;
   if (workspace == nullptr || (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return BITSORT_ERR_INVALID_ARG;
   RadixPlan p;
-  make_radix_plan(n, key_bits, &p);
+  make_radix_plan(n, key_bits, 4, false, &p);
   if (ws_bytes < p.bytes) return BITSORT_ERR_NO_MEMORY;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (n == 0) return hipMemsetAsync(workspace, 0, sizeof(Status), s) == hipSuccess ? BITSORT_OK : BITSORT_ERR_HIP;
   if ((rc = init_kernels()) != BITSORT_OK) return rc;
-  return run_radix(p, keys, n, key_bits, 0u, out, workspace, s);
+  return run_radix<uint32_t, false>(p, keys, nullptr, n, key_bits, 0u, out, nullptr, workspace, s);
 }
 
 int bitsort_count_u32(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32_t* out, bitsort_stream_t stream) {
@@ -769,12 +802,21 @@ int bitsort_count_u32(const uint32_t* keys, uint64_t n, uint32_t range_bits, uin
 }
 
 int bitsort_radix_u32(const uint32_t* keys, uint64_t n, uint32_t key_bits, uint32_t* out, bitsort_stream_t stream) {
-  return radix_on_stream(keys, n, key_bits, 0u, out, stream);
+  return radix_on_stream<uint32_t, false>(keys, nullptr, n, key_bits, 0u, out, nullptr, stream);
 }
 
 int bitsort_radix_i32(const int32_t* keys, uint64_t n, int32_t* out, bitsort_stream_t stream) {
-  return radix_on_stream(reinterpret_cast<const uint32_t*>(keys), n, 32, 0x80000000u, reinterpret_cast<uint32_t*>(out),
-                         stream);
+  return radix_on_stream<uint32_t, false>(reinterpret_cast<const uint32_t*>(keys), nullptr, n, 32, 0x80000000u,
+                                          reinterpret_cast<uint32_t*>(out), nullptr, stream);
+}
+
+int bitsort_radix_u64(const uint64_t* keys, uint64_t n, uint32_t key_bits, uint64_t* out, bitsort_stream_t stream) {
+  return radix_on_stream<uint64_t, false>(keys, nullptr, n, key_bits, 0ull, out, nullptr, stream);
+}
+
+int bitsort_radix_pairs_u32(const uint32_t* keys, const uint32_t* values, uint64_t n, uint32_t key_bits,
+                            uint32_t* out_keys, uint32_t* out_values, bitsort_stream_t stream) {
+  return radix_on_stream<uint32_t, true>(keys, values, n, key_bits, 0u, out_keys, out_values, stream);
 }
 
 int bitsort_i32(const int32_t* keys_s, uint64_t n, uint32_t range_bits, int32_t* out_s, bitsort_stream_t stream) {

@@ -142,3 +142,70 @@ def test_repeatable():
     first = bs.radix_sort(k, 32).clone()
     for _ in range(3):
         assert torch.equal(bs.radix_sort(k, 32), first)
+
+
+# ---- 64-bit keys and key-value records ---------------------------------------------------
+
+def _dev64(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64).copy()).cuda()
+
+
+@pytest.mark.parametrize("n", [1, 63, 2047, 2048, 2049, 100_003, 1_000_000])
+def test_u64_full_width(o, n):
+    import paper_1312_0138_amd as bs
+    rng = np.random.default_rng(n + 64)
+    keys = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+    got = bs.radix_sort_u64(_dev64(keys), 64).cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(got, o.bitwise_sort1_u64(keys, 64))
+    st = bs.status()
+    assert st.flags == 0 and st.count == n
+
+
+@pytest.mark.parametrize("key_bits", [0, 8, 33, 40, 57])
+def test_u64_key_bits_and_out_of_range(o, key_bits):
+    import paper_1312_0138_amd as bs
+    rng = np.random.default_rng(key_bits)
+    n = 30_000
+    keys = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)  # bits above key_bits set: placed by low bits, stably
+    got = bs.radix_sort_u64(_dev64(keys), key_bits).cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(got, o.bitwise_sort1_u64(keys, key_bits))
+    assert bs.status().flags == (1 if key_bits < 64 else 0)
+
+
+def test_u64_in_place_and_duplicates(o):
+    import paper_1312_0138_amd as bs
+    rng = np.random.default_rng(9)
+    pool = rng.integers(0, 1 << 64, size=100, dtype=np.uint64)
+    keys = pool[rng.integers(0, 100, size=50_001)]
+    k = _dev64(keys)
+    bs.radix_sort_u64(k, 64, out=k)
+    np.testing.assert_array_equal(k.cpu().numpy().view(np.uint64), o.bitwise_sort1_u64(keys, 64))
+
+
+@pytest.mark.parametrize("n,key_bits", [(1, 32), (8191, 32), (8192, 32), (8193, 32), (300_001, 32), (200_000, 20),
+                                        (50_000, 9), (1 << 22, 32)])
+def test_pairs(o, n, key_bits):
+    import paper_1312_0138_amd as bs
+    rng = np.random.default_rng(n + key_bits)
+    keys = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    keys[::3] = keys[0]  # many equal keys: their values must keep input order
+    vals = rng.permutation(n).astype(np.uint32)
+    ok, ov = bs.radix_sort_pairs(to_dev(keys), to_dev(vals), key_bits)
+    wk, wv = o.bitwise_sort1_pairs(keys, vals, key_bits)
+    np.testing.assert_array_equal(to_np(ok), wk)
+    np.testing.assert_array_equal(to_np(ov), wv)
+    assert bs.status().flags == (1 if key_bits < 32 and int(keys.max()) >> key_bits else 0)
+
+
+@pytest.mark.parametrize("key_bits", [16, 24])
+def test_pairs_in_place(o, key_bits):
+    import paper_1312_0138_amd as bs
+    rng = np.random.default_rng(key_bits)
+    keys = rng.integers(0, 1 << key_bits, size=70_000, dtype=np.uint64).astype(np.uint32)
+    vals = np.arange(keys.size, dtype=np.uint32)
+    k, v = to_dev(keys), to_dev(vals)
+    bs.radix_sort_pairs(k, v, key_bits, out_keys=k, out_values=v)
+    wk, wv = o.bitwise_sort1_pairs(keys, vals, key_bits)
+    np.testing.assert_array_equal(to_np(k), wk)
+    np.testing.assert_array_equal(to_np(v), wv)

@@ -52,6 +52,12 @@ def test_host_argument_checks(lib):
     assert E.bitsort_count_u32(fake, 100, 20, fake + 4, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_i32(fake, 10, 33, fake + 4096, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_radix_i32(fake, 100, fake + 4, 0) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_radix_u64(fake, 10, 65, fake + 4096, 0) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_radix_u64(fake, 100, 64, fake + 8, 0) == E.BITSORT_ERR_INVALID_ARG
+    big = fake + (1 << 24)
+    assert E.bitsort_radix_pairs_u32(fake, big, 100, 32, fake + 4096, fake + 4096, 0) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_radix_pairs_u32(fake, big, 100, 32, fake + 4096, fake + 8, 0) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_radix_pairs_u32(fake, 0, 100, 32, fake + 4096, big, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_radix_u32_ws(fake, 10, 32, fake + 4096, fake, 16, 0) == E.BITSORT_ERR_NO_MEMORY
 
 
