@@ -19,6 +19,10 @@ Workloads (default: plain-uniform):
   radix-uniform   2^26 uint32 keys uniform in [0, 2^32) with repeats, through
                   the LSD radix sort (the paper's Algorithm 1, 8-bit digits)
   radix-sparse    the plain-sparse input through the LSD radix sort
+  radix-u64       2^25 uint64 keys through the 64-bit radix sort (8 passes)
+  radix-pairs     2^26 uint32 keys with uint32 values (key-value radix sort)
+  signed-uniform  2^26 distinct int32 keys in [-2^27, 2^27), signed bitmap sort
+  count-uniform   2^26 keys in [0, 2^24) with repeats, counting (multiset) sort
   batch           4096 arrays, sizes log-uniform in [256, 2^20], range the
                   power of two >= 4n: one batched launch vs 4096 plain launches
   serve           20,000 sort requests, sizes log-uniform in [2^10, 2^24],
@@ -54,6 +58,14 @@ PLAIN = {
                           desc="2^26 uint32 keys uniform in [0, 2^32) with repeats; LSD radix, 4 passes of 8-bit digits"),
     "radix-sparse": dict(n=1 << 24, rb=32, cfg=3, sorter="radix",
                          desc="the plain-sparse input (2^24 distinct keys in [0, 2^32)) through the LSD radix sort"),
+    "radix-u64": dict(n=1 << 25, rb=64, cfg=7, sorter="radix64",
+                      desc="2^25 uint64 keys uniform in [0, 2^64) with repeats; LSD radix, 8 passes"),
+    "radix-pairs": dict(n=1 << 26, rb=32, cfg=8, sorter="pairs",
+                        desc="2^26 uint32 keys uniform in [0, 2^32) with repeats, each with a uint32 value; 4 passes"),
+    "signed-uniform": dict(n=1 << 26, rb=28, cfg=9, sorter="signed",
+                           desc="2^26 distinct int32 keys uniform in [-2^27, 2^27); bitmap sort with the signed shift"),
+    "count-uniform": dict(n=1 << 26, rb=24, cfg=10, sorter="count",
+                          desc="2^26 uint32 keys uniform in [0, 2^24), about 4 repeats per value; counting sort"),
 }
 
 
@@ -91,11 +103,21 @@ def algorithmic_bytes(n: int, rb: int, emit_path: str) -> dict:
     return ab
 
 
-def radix_algorithmic_bytes(n: int, key_bits: int) -> dict:
+def radix_algorithmic_bytes(n: int, key_bits: int, elem_bytes: int = 4) -> dict:
     """The LSD radix sort's own bytes: every digit pass reads and writes the
-    n keys once (8n); the histogram pass and look-back state are overhead."""
+    n elements once (2 x elem_bytes x n: 8n for uint32 keys, 16n for uint64
+    keys or key-value records); the histogram pass and look-back state are
+    overhead."""
     passes = (key_bits + 7) // 8
-    return {"k_radix_pass": 8 * n, "k_radix_hist": 4 * n, "k_radix_scan": 0, "path": passes * 8 * n}
+    e = elem_bytes
+    return {"k_radix_pass": 2 * e * n, "k_radix_hist": 0, "k_radix_scan": 0, "path": passes * 2 * e * n}
+
+
+def count_algorithmic_bytes(n: int, rb: int) -> dict:
+    """The counting sort credited like the bitmap: keys in, one pass over the
+    key range's presence (R/8), keys out; the counters themselves stay in LDS."""
+    r8 = (1 << rb) // 8
+    return {"k_partition": 4 * n, "k_count_slice": r8 + 4 * n, "k_finish": 0, "path": 8 * n + r8}
 
 
 def read_traffic(kernel: str, workload: str, digest: str):
@@ -117,59 +139,113 @@ def read_traffic(kernel: str, workload: str, digest: str):
         return None
 
 
-def cpu_baseline(keys_host, rb: int, budget_s: float = 12.0, max_reps: int = 5, sorter: str = "bitmap"):
-    """The oracle, single-threaded, timed on the host: (Gkeys/s, reps, out).
-    The radix sort's oracle is the paper's Algorithm 1 over rb bit passes."""
+def cpu_baseline(host, sorter: str, rb: int, budget_s: float = 12.0, max_reps: int = 5):
+    """The oracle, single-threaded, timed on the host: (Gkeys/s, reps, median s, out)."""
     import oracle
-    o = oracle.default()
+    fn = oracle_fn(oracle.default(), sorter, rb)
+    n = host[0].size if sorter == "pairs" else host.size
     times, out = [], None
     t_start = time.perf_counter()
     for _ in range(max_reps):
         t0 = time.perf_counter()
-        if sorter == "radix":
-            out = o.bitwise_sort1(keys_host, rb)
-        else:
-            out, _, _ = o.bitmap_sort(keys_host, rb)
+        out = fn(host)
         times.append(time.perf_counter() - t0)
         if time.perf_counter() - t_start > budget_s:
             break
     med = statistics.median(times)
-    return keys_host.size / med / 1e9, len(times), med, out
+    return n / med / 1e9, len(times), med, out
 
 
 def make_plain_inputs(bs, torch, spec, workload, pool):
+    """Device input buffers (a tuple of keys and values for the pairs sort)."""
     from paper_1312_0138_amd import inputs
     n, rb, cfg = spec["n"], spec["rb"], spec["cfg"]
+    sorter = spec.get("sorter", "bitmap")
     bufs = []
-    if workload == "radix-uniform":
-        for rep in range(pool):
+    if sorter in ("radix64", "pairs", "count") or workload in ("radix-uniform", "plain-clustered"):
+        reps = 1 if workload == "plain-clustered" else pool
+        for rep in range(reps):
             host = host_input(spec, workload, n, rep)
-            bufs.append(torch.from_numpy(host.view("int32")).cuda())
-        return bufs, n
-    if workload == "plain-clustered":
-        host = inputs.clustered(1 << 26, rb, inputs.config_seed(cfg, 1))
-        n = host.size
-        t = torch.from_numpy(host.view("int32")).cuda()
-        bufs = [t] + [t.clone() for _ in range(pool - 1)]
+            if sorter == "pairs":
+                bufs.append(tuple(torch.from_numpy(h.view("int32")).cuda() for h in host))
+            elif sorter == "radix64":
+                bufs.append(torch.from_numpy(host.view("int64")).cuda())
+            else:
+                bufs.append(torch.from_numpy(host.view("int32")).cuda())
+        n = host[0].size if sorter == "pairs" else host.size
+        while len(bufs) < pool:
+            bufs.append(bufs[0].clone())
         return bufs, n
     for rep in range(pool):
         t = torch.empty(n, dtype=torch.int32, device="cuda")
         bs.generate(n, rb, inputs.config_seed(cfg, rep), out=t)
+        if sorter == "signed":
+            t -= 1 << (rb - 1)  # onto [-2^(rb-1), 2^(rb-1))
         bufs.append(t)
     return bufs, n
 
 
 def host_input(spec, workload, n, rep=0):
+    """The same inputs on the host (numpy), for the oracle."""
     import numpy as np
 
     from paper_1312_0138_amd import inputs
     rb, cfg = spec["rb"], spec["cfg"]
-    if workload == "radix-uniform":
-        rng = np.random.default_rng(inputs.config_seed(cfg, rep))
-        return rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    sorter = spec.get("sorter", "bitmap")
+    rng = np.random.default_rng(inputs.config_seed(cfg, rep))
+    if workload == "radix-uniform" or sorter == "pairs":
+        keys = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+        return (keys, np.arange(n, dtype=np.uint32)) if sorter == "pairs" else keys
+    if sorter == "radix64":
+        return rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+    if sorter == "count":
+        return rng.integers(0, 1 << rb, size=n, dtype=np.uint64).astype(np.uint32)
     if workload == "plain-clustered":
         return inputs.clustered(1 << 26, rb, inputs.config_seed(cfg, 1))
-    return inputs.distinct_uniform(n, rb, inputs.config_seed(cfg, 0))
+    keys = inputs.distinct_uniform(n, rb, inputs.config_seed(cfg, rep))
+    if sorter == "signed":
+        return (keys.astype(np.int64) - (1 << (rb - 1))).astype(np.int32)
+    return keys
+
+
+def sort_fn(bs, sorter):
+    """The library call a step makes: fn(input buffer, rb, output buffer)."""
+    return {
+        "bitmap": lambda x, rb, out: bs.sort(x, rb, out),
+        "signed": lambda x, rb, out: bs.sort_signed(x, rb, out),
+        "count": lambda x, rb, out: bs.sort_multiset(x, rb, out),
+        "radix": lambda x, rb, out: bs.radix_sort(x, rb, out),
+        "radix64": lambda x, rb, out: bs.radix_sort_u64(x, rb, out),
+        "pairs": lambda x, rb, out: bs.radix_sort_pairs(x[0], x[1], rb, out[0], out[1]),
+    }[sorter]
+
+
+def oracle_fn(o, sorter, rb):
+    """The oracle's version of the same sort: fn(host input) -> expected output."""
+    import numpy as np
+    if sorter == "signed":
+        def signed(keys):
+            shift = 1 << (rb - 1)
+            out, _, _ = o.bitmap_sort((keys.astype(np.int64) + shift).astype(np.uint32), rb)
+            return (out.astype(np.int64) - shift).astype(np.int32)
+        return signed
+    return {
+        "bitmap": lambda keys: o.bitmap_sort(keys, rb)[0],
+        "count": lambda keys: o.counting_sort(keys, rb)[0],
+        "radix": lambda keys: o.bitwise_sort1(keys, rb),
+        "radix64": lambda keys: o.bitwise_sort1_u64(keys, rb),
+        "pairs": lambda kv: o.bitwise_sort1_pairs(kv[0], kv[1], rb),
+    }[sorter]
+
+
+ORACLE_KIND = {
+    "bitmap": "single-threaded C oracle (bitmap sort)",
+    "signed": "single-threaded C oracle (bitmap sort of the shifted keys)",
+    "count": "single-threaded C oracle (counting sort)",
+    "radix": "single-threaded C oracle (Algorithm 1, one-bit passes)",
+    "radix64": "single-threaded C oracle (Algorithm 1 for uint64, 64 one-bit passes)",
+    "pairs": "single-threaded C oracle (Algorithm 1 on key-value records)",
+}
 
 
 def bench_plain(args, workload):
@@ -181,21 +257,27 @@ def bench_plain(args, workload):
 
     spec = PLAIN[workload]
     rb = spec["rb"]
-    radix = spec.get("sorter") == "radix"
-    sort = bs.radix_sort if radix else bs.sort
+    sorter = spec.get("sorter", "bitmap")
+    bitmap_like = sorter in ("bitmap", "signed")
+    radix = sorter in ("radix", "radix64", "pairs")
+    sort = sort_fn(bs, sorter)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    elem = {"radix64": 8, "pairs": 8}.get(sorter, 4)
     pool = args.pool
     if pool == 0:
-        per = 4 * (spec["n"] or (1 << 26))
+        per = elem * (spec["n"] or (1 << 26))
         pool = max(2, min(128, -(-2 * MALL_BYTES // per)))
     bufs, n = make_plain_inputs(bs, torch, spec, workload, pool)
-    out = torch.empty(n, dtype=torch.int32, device="cuda")
-    tuned = bs.autotune(n, rb, reps=3) if args.autotune and not radix else None
-    plan = None if radix else bs.plan_info(n, rb)
+    if sorter == "pairs":
+        out = (torch.empty(n, dtype=torch.int32, device="cuda"), torch.empty(n, dtype=torch.int32, device="cuda"))
+    else:
+        out = torch.empty_like(bufs[0])
+    tuned = bs.autotune(n, rb, reps=3) if args.autotune and sorter == "bitmap" else None
+    plan = bs.plan_info(n, rb) if bitmap_like else None
 
     graphs = None
-    if args.graph and not radix:
+    if args.graph and sorter == "bitmap":
         # one captured graph per input buffer: replays allocate and launch nothing else
         graphs = [bs.Graph.plain(b, rb, out) for b in bufs]
 
@@ -249,7 +331,12 @@ def bench_plain(args, workload):
 
     ms_per_step = total_ms / args.steps
     value = n / (ms_per_step / 1e3) / 1e9
-    ab = radix_algorithmic_bytes(n, rb) if radix else algorithmic_bytes(n, rb, plan["emit_path"])
+    if radix:
+        ab = radix_algorithmic_bytes(n, rb, elem)
+    elif sorter == "count":
+        ab = count_algorithmic_bytes(n, rb)
+    else:
+        ab = algorithmic_bytes(n, rb, plan["emit_path"])
     kernels = {k: {"launches": int(l), "avg_us": round(1e3 * ms / max(l, 1), 3)} for k, (l, ms) in prof.items()}
     dom = max(prof, key=lambda k: prof[k][1])
     dom_avg_s = prof[dom][1] / prof[dom][0] / 1e3
@@ -259,15 +346,21 @@ def bench_plain(args, workload):
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 "traffic": read_traffic(dom, workload, digest), "algorithmic_bytes": ab[dom]}
     path_gbps = ab["path"] / (ms_per_step / 1e3) / 1e9
+    if bitmap_like:
+        config = {"workload": workload, "description": spec["desc"], "n": n, "range_bits": rb,
+                  "input_pool": len(bufs), "slice_bits": plan["slice_bits"], "tile_log2": plan["tile_log2"],
+                  "slices": plan["buckets"], "emit_path": plan["emit_path"]}
+    else:
+        config = {"workload": workload, "description": spec["desc"], "n": n,
+                  ("key_bits" if radix else "range_bits"): rb, "input_pool": len(bufs)}
+        if radix:
+            config["passes"] = (rb + 7) // 8
     result = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": ({"workload": workload, "description": spec["desc"], "n": n, "key_bits": rb,
-                    "input_pool": len(bufs), "passes": (rb + 7) // 8} if radix else
-                   {"workload": workload, "description": spec["desc"], "n": n, "range_bits": rb,
-                    "input_pool": len(bufs), "slice_bits": plan["slice_bits"], "tile_log2": plan["tile_log2"],
-                    "slices": plan["buckets"], "emit_path": plan["emit_path"]}),
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"signed": "i32", "radix64": "u64", "pairs": "u32+u32"}.get(sorter, "u32"), "data": "synthetic",
+        "config": config,
         "p50_ms": round(p50, 5), "p99_ms": round(p99, 5),
         "profiled_ms_per_step": round(sum(step_ms) / len(step_ms), 5),
         "roofline": roofline,
@@ -278,18 +371,25 @@ def bench_plain(args, workload):
         "autotuned": tuned,
     }
     if not args.no_cpu_baseline:
-        keys_host = host_input(spec, workload, n)
-        gk, reps, med, want = cpu_baseline(keys_host, rb, sorter="radix" if radix else "bitmap")
+        host = host_input(spec, workload, n)
+        gk, reps, med, want = cpu_baseline(host, sorter, rb)
         # the GPU result for the same input must equal the oracle's
-        check_in = torch.from_numpy(keys_host.view(np.int32)).cuda()
-        got = sort(check_in, rb).cpu().numpy().view(np.uint32)
-        if not np.array_equal(got, want):
+        if sorter == "pairs":
+            dev = tuple(torch.from_numpy(h.view(np.int32)).cuda() for h in host)
+            got_k, got_v = sort(dev, rb, (torch.empty_like(dev[0]), torch.empty_like(dev[1])))
+            same = (np.array_equal(got_k.cpu().numpy().view(np.uint32), want[0])
+                    and np.array_equal(got_v.cpu().numpy().view(np.uint32), want[1]))
+        else:
+            view = {"radix64": np.int64, "signed": np.int32}.get(sorter, np.int32)
+            dev = torch.from_numpy(host.view(view)).cuda()
+            got = sort(dev, rb, torch.empty_like(dev)).cpu().numpy().view(want.dtype)
+            same = np.array_equal(got, want)
+        if not same:
             print(json.dumps({"error": "GPU output differs from the CPU oracle", "workload": workload}))
             sys.exit(3)
         result["cpu_baseline"] = {"value": round(gk, 4), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
                                   "sample": f"full {workload} input (n={n}), {reps} repetition(s), "
-                                            f"median {med:.3f} s per sort; single-threaded C oracle"
-                                            + (" (Algorithm 1, 32 one-bit passes)" if radix else ""),
+                                            f"median {med:.3f} s per sort; {ORACLE_KIND[sorter]}",
                                   "host_cores": os.cpu_count()}
         result["verified_against_oracle"] = True
     return result
