@@ -151,6 +151,31 @@ int bitsort_batch_u32(const uint32_t *keys, const uint64_t *offsets, uint32_t nu
 int bitsort_batch_status(bitsort_stream_t stream, bitsort_status_t *status, uint32_t num_segments);
 
 /*
+ * Pointer-array batch: count independent arrays, each sorted by the plain
+ * path's method (partition into LDS slices, mark, scan, emit from LDS), all
+ * arrays in one launch of each kernel -- any range_bits up to 32 per array,
+ * and every key read once by the partition (the segmented launch above reads
+ * a segment once per 2^20-bit slice of its range).
+ *
+ *   keys, out    host arrays of count device pointers; array a is keys[a][0 ..
+ *                n[a]) and its result goes to out[a][0 .. n[a]).  out[a] ==
+ *                keys[a] is allowed; any other overlap between an array's
+ *                input and output is rejected; different arrays must not share
+ *                memory.
+ *   n            host array of count sizes, n[a] <= 2^range_bits[a], < 2^32.
+ *   range_bits   host array of count widths, 0..32.
+ *   count        1 .. BITSORT_BATCH_MAX_SEGMENTS.
+ *   stream       HIP stream; the call enqueues work (the host arrays may be
+ *                reused as soon as it returns).
+ *
+ * Per-array status (flags and keys written) with bitsort_batch_status on the
+ * same stream, as for bitsort_batch_u32.  Errors as bitsort_u32, checked per
+ * array on the host.
+ */
+int bitsort_batch_ptr_u32(const uint32_t *const *keys, const uint64_t *n, const uint8_t *range_bits,
+                          uint32_t *const *out, uint32_t count, bitsort_stream_t stream);
+
+/*
  * LSD radix sort of arbitrary uint32 keys, duplicates kept: the paper's own
  * sort (Algorithm 1, Section V; correctness by Theorem 1), a stable partition
  * by each key bit from bit 0 up, run here as ceil(key_bits / 8) stable passes
@@ -420,7 +445,8 @@ int bitsort_digest_u32(const uint32_t *data, uint64_t n, uint64_t *digest, bitso
  */
 typedef struct bitsort_profile_entry {
     char kernel[32];      /* k_partition, k_slice, k_emit, k_finish, k_direct, k_batch_plan, k_batch_run,
-                             k_radix_hist, k_radix_scan, k_radix_pass, k_count_slice */
+                             k_radix_hist, k_radix_scan, k_radix_pass, k_count_slice,
+                             k_partition_multi, k_slice_multi, k_finish_multi */
     uint64_t launches;
     double total_ms;
 } bitsort_profile_entry_t;

@@ -18,7 +18,7 @@ __all__ = [
     "plan_info", "BitsortError", "Status", "STATUS_OUT_OF_RANGE", "STATUS_DUPLICATE",
     "STATUS_BAD_SEGMENT", "Graph", "autotune", "autotune_batch", "tuning_save", "tuning_load",
     "tuning_clear", "radix_sort", "radix_workspace_bytes", "radix_sort_ws", "STATUS_TIMEOUT", "sort_signed", "radix_sort_signed", "sort_multiset", "radix_sort_u64",
-    "radix_sort_pairs",
+    "radix_sort_pairs", "sort_many",
 ]
 
 
@@ -220,6 +220,31 @@ def sort_batch(keys, offsets, range_bits, out=None, stream=None):
     _lib.check(_lib.bitsort_batch_u32(keys.data_ptr(), offsets.data_ptr(), nseg, range_bits.data_ptr(),
                                       out.data_ptr(), keys.numel(), _stream(stream)), "bitsort_batch_u32")
     return out
+
+
+def sort_many(arrays, range_bits, outs=None, stream=None):
+    """Sort each uint32 device tensor of ``arrays`` (distinct keys below
+    2^range_bits[i]) into ``outs[i]`` with one launch of each plain-path
+    kernel for all of them; returns the outputs."""
+    import numpy as np
+    torch = _torch()
+    count = len(arrays)
+    if outs is None:
+        outs = [torch.empty_like(a) for a in arrays]
+    if len(outs) != count or len(range_bits) != count:
+        raise ValueError("arrays, outs and range_bits differ in length")
+    for a, o in zip(arrays, outs):
+        _check_u32(a, "arrays[i]")
+        _check_u32(o, "outs[i]")
+        if o.numel() != a.numel():
+            raise ValueError("outs[i] must have as many elements as arrays[i]")
+    kp = np.array([a.data_ptr() for a in arrays], dtype=np.uint64)
+    op = np.array([o.data_ptr() for o in outs], dtype=np.uint64)
+    nn = np.array([a.numel() for a in arrays], dtype=np.uint64)
+    rb = np.array(range_bits, dtype=np.uint8)
+    _lib.check(_lib.bitsort_batch_ptr_u32(kp.ctypes.data, nn.ctypes.data, rb.ctypes.data, op.ctypes.data, count,
+                                          _stream(stream)), "bitsort_batch_ptr_u32")
+    return outs
 
 
 def batch_status(num_segments: int, stream=None):

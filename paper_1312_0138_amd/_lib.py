@@ -68,6 +68,7 @@ _SIGS = {
     "bitsort_workspace_status": (_c.c_int, [_vp, _vp, _c.POINTER(Status)]),
     "bitsort_batch_u32": (_c.c_int, [_vp, _vp, _u32, _vp, _vp, _u64, _vp]),
     "bitsort_batch_status": (_c.c_int, [_vp, _c.POINTER(Status), _u32]),
+    "bitsort_batch_ptr_u32": (_c.c_int, [_vp, _vp, _vp, _vp, _u32, _vp]),
     "bitsort_generate_u32": (_c.c_int, [_vp, _u64, _u64, _u32, _u64, _vp]),
     "bitsort_debug_bitmap_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
     "bitsort_debug_prefix_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
@@ -184,6 +185,11 @@ def bitsort_radix_workspace_bytes(n: int, key_bits: int) -> int:
 
 def bitsort_radix_u32_ws(keys: int, n: int, key_bits: int, out: int, ws: int, ws_bytes: int, stream: int) -> int:
     return lib().bitsort_radix_u32_ws(keys, n, key_bits, out, ws, ws_bytes, stream)
+
+
+def bitsort_batch_ptr_u32(keys: int, n: int, range_bits: int, out: int, count: int, stream: int) -> int:
+    """keys/n/range_bits/out: addresses of host arrays (see the header)."""
+    return lib().bitsort_batch_ptr_u32(keys, n, range_bits, out, count, stream)
 
 
 def bitsort_get_status(stream: int) -> tuple[int, Status]:

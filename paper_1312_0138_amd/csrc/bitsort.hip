@@ -86,6 +86,9 @@ namespace {
 #include "count_kernels.inc"
 
 // ---------------------------------------------------------------------------
+#include "multi_kernels.inc"
+
+// ---------------------------------------------------------------------------
 // Host side.
 
 struct Plan {
@@ -223,6 +226,8 @@ int init_kernels() {
     set_lds_attr(k_slice<kSliceBlock, kSliceUnroll>, kLdsBytes);
     set_lds_attr(k_direct<kDirectBlock>, kLdsBytes);
     set_lds_attr(k_count_slice<kSliceBlock, kSliceUnroll>, kLdsBytes);
+    set_lds_attr(k_partition_multi, kLdsBytes);
+    set_lds_attr(k_slice_multi<kSliceBlock, kSliceUnroll>, kLdsBytes);
     set_lds_attr(k_batch_run<256>, kLdsBytes);
     set_lds_attr(k_batch_run<512>, kLdsBytes);
     set_lds_attr(k_batch_run<1024>, kLdsBytes);
@@ -238,11 +243,12 @@ int launch_status() {
 // Kernel timing (bitsort_profile_*): events bracketing each launch.
 enum KernelId : int {
   kKPartition = 0, kKSlice, kKEmit, kKFinish, kKDirect, kKBatchPlan, kKBatchRun, kKRadixHist, kKRadixScan,
-  kKRadixPass, kKCountSlice, kKCount
+  kKRadixPass, kKCountSlice, kKPartitionMulti, kKSliceMulti, kKFinishMulti, kKCount
 };
 const char* const kKernelNames[kKCount] = {"k_partition", "k_slice",      "k_emit",       "k_finish",
                                            "k_direct",    "k_batch_plan", "k_batch_run",  "k_radix_hist",
-                                           "k_radix_scan", "k_radix_pass", "k_count_slice"};
+                                           "k_radix_scan", "k_radix_pass", "k_count_slice",
+                                           "k_partition_multi", "k_slice_multi", "k_finish_multi"};
 struct PendingTiming {
   int kernel;
   hipEvent_t start, stop;
@@ -389,6 +395,102 @@ int run_count(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
   }
   LaunchTimer timer(kKFinish, stream);
   hipLaunchKernelGGL((k_finish<kSliceBlock>), dim3(1), dim3(kSliceBlock), 0, stream, n, p.nb, info, status, out);
+  return launch_status();
+}
+
+// ---- many arrays through the plain path in one launch per kernel -------------
+
+// Workspace of a multi launch: [header][status x count][descriptors]
+// [slice info][tile tables][staging].
+struct MultiPlan {
+  std::vector<MultiDesc> desc;
+  uint32_t tiles = 0, slices = 0, max_nb = 1, max_sb = kMinSliceBits;
+  uint64_t table_words = 0;
+  size_t off_status = 0, off_desc = 0, off_info = 0, off_table = 0, off_staging = 0, bytes = 0;
+};
+
+int check_multi_args(const uint32_t* const* keys, const uint64_t* n, const uint8_t* range_bits,
+                     uint32_t* const* out, uint32_t count) {
+  if (count == 0 || count > BITSORT_BATCH_MAX_SEGMENTS || keys == nullptr || n == nullptr ||
+      range_bits == nullptr || out == nullptr)
+    return BITSORT_ERR_INVALID_ARG;
+  for (uint32_t a = 0; a < count; ++a) {
+    int rc = check_args(keys[a], n[a], range_bits[a], out[a]);
+    if (rc != BITSORT_OK) return rc;
+  }
+  return BITSORT_OK;
+}
+
+// Per array: slices of 2^sb bits aiming at 256 slices (sb in [10, 20], at
+// most 4096 slices), tiles of kMultiTile keys.
+void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8_t* range_bits,
+                     uint32_t* const* out, uint32_t count, MultiPlan* p) {
+  p->desc.resize(count);
+  for (uint32_t a = 0; a < count; ++a) {
+    MultiDesc& d = p->desc[a];
+    const uint32_t rb = range_bits[a];
+    uint32_t sb = rb > 8 ? rb - 8 : rb;
+    sb = std::max({sb, kMinSliceBits, rb > kMaxBucketsLog2 ? rb - kMaxBucketsLog2 : 0u});
+    sb = std::min(sb, kMaxSliceBits);
+    d.keys = keys[a];
+    d.out = out[a];
+    d.n = n[a];
+    d.rb = rb;
+    d.sb = sb;
+    d.nb = rb > sb ? 1u << (rb - sb) : 1u;
+    d.nt = static_cast<uint32_t>((n[a] + kMultiTile - 1) / kMultiTile);
+    d.tile0 = p->tiles;
+    d.slice0 = p->slices;
+    d.table_off = p->table_words;
+    p->tiles += d.nt;
+    p->slices += d.nb;
+    p->table_words += static_cast<uint64_t>(d.nt) * (d.nb + 1);
+    p->max_nb = std::max(p->max_nb, d.nb);
+    p->max_sb = std::max(p->max_sb, d.sb);
+  }
+  size_t o = kHeaderBytes;
+  p->off_status = o;
+  o = align256(o + sizeof(SegStatus) * count);
+  p->off_desc = o;
+  o = align256(o + sizeof(MultiDesc) * count);
+  p->off_info = o;
+  o = align256(o + 24ull * p->slices);
+  p->off_table = o;
+  o = align256(o + 4ull * p->table_words);
+  p->off_staging = o;
+  o = align256(o + 4ull * p->tiles * kMultiTile);
+  p->bytes = o;
+}
+
+// Enqueue the three multi kernels; the descriptors must already be on the
+// device at ws + off_desc.
+int run_multi(const MultiPlan& p, uint32_t count, void* ws, hipStream_t stream) {
+  int rc = init_kernels();
+  if (rc != BITSORT_OK) return rc;
+  char* base = static_cast<char*>(ws);
+  const MultiDesc* desc = reinterpret_cast<const MultiDesc*>(base + p.off_desc);
+  uint64_t* info = reinterpret_cast<uint64_t*>(base + p.off_info);
+  uint32_t* table = reinterpret_cast<uint32_t*>(base + p.off_table);
+  uint32_t* staging = reinterpret_cast<uint32_t*>(base + p.off_staging);
+  if (p.tiles > 0) {
+    LaunchTimer timer(kKPartitionMulti, stream);
+    const size_t part_lds = 4ull * (32 + round_up4(p.max_nb) + kMultiTile);
+    hipLaunchKernelGGL(k_partition_multi, dim3(p.tiles), dim3(kMultiBlock), part_lds, stream, desc, count, staging,
+                       table);
+    if ((rc = launch_status()) != BITSORT_OK) return rc;
+  }
+  {
+    LaunchTimer timer(kKSliceMulti, stream);
+    const uint32_t stage_cap = stage_cap_for(p.max_sb);
+    const uint32_t grid = 8u * ((p.slices + 7u) / 8u);
+    hipLaunchKernelGGL((k_slice_multi<kSliceBlock, kSliceUnroll>), dim3(grid), dim3(kSliceBlock),
+                       slice_lds_bytes(p.max_sb, stage_cap), stream, desc, count, p.slices, staging, table, info,
+                       stage_cap);
+    if ((rc = launch_status()) != BITSORT_OK) return rc;
+  }
+  LaunchTimer timer(kKFinishMulti, stream);
+  hipLaunchKernelGGL(k_finish_multi<kSliceBlock>, dim3(count), dim3(kSliceBlock), 0, stream, desc, info,
+                     reinterpret_cast<Status*>(base + p.off_status));
   return launch_status();
 }
 
@@ -613,6 +715,9 @@ struct StreamCtx {
   void* batch_ws = nullptr;
   size_t batch_bytes = 0;
   uint32_t batch_segments = 0;
+  void* desc_host = nullptr;        // pinned staging of bitsort_batch_ptr_u32's descriptors
+  size_t desc_host_bytes = 0;
+  hipEvent_t desc_copied = nullptr;  // the last descriptor upload has left desc_host
 };
 std::mutex g_mu;
 std::map<std::pair<int, void*>, StreamCtx> g_ctx;
@@ -919,6 +1024,44 @@ int bitsort_batch_u32(const uint32_t* keys, const uint64_t* offsets, uint32_t nu
   if (rc != BITSORT_OK) return rc;
   c.batch_segments = num_segments;
   return run_batch(keys, offsets, num_segments, range_bits, out, max_keys, c.batch_ws, s, t);
+}
+
+int bitsort_batch_ptr_u32(const uint32_t* const* keys, const uint64_t* n, const uint8_t* range_bits,
+                          uint32_t* const* out, uint32_t count, bitsort_stream_t stream) {
+  int rc = check_multi_args(keys, n, range_bits, out, count);
+  if (rc != BITSORT_OK) return rc;
+  MultiPlan p;
+  make_multi_plan(keys, n, range_bits, out, count, &p);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  StreamCtx& c = ctx_for(stream);
+  rc = grow(&c.batch_ws, &c.batch_bytes, p.bytes, s);
+  if (rc != BITSORT_OK) return rc;
+  c.batch_segments = count;
+  // Descriptors go up from a pinned buffer of the stream's own; before it is
+  // refilled, the previous upload from it must have finished.
+  const size_t dbytes = sizeof(MultiDesc) * count;
+  if (c.desc_copied != nullptr && hipEventSynchronize(c.desc_copied) != hipSuccess) return BITSORT_ERR_HIP;
+  if (c.desc_copied == nullptr && hipEventCreateWithFlags(&c.desc_copied, hipEventDisableTiming) != hipSuccess) {
+    c.desc_copied = nullptr;
+    return BITSORT_ERR_HIP;
+  }
+  if (c.desc_host_bytes < dbytes) {
+    if (c.desc_host != nullptr) (void)hipHostFree(c.desc_host);
+    c.desc_host = nullptr;
+    c.desc_host_bytes = 0;
+    if (hipHostMalloc(&c.desc_host, dbytes, hipHostMallocDefault) != hipSuccess) {
+      c.desc_host = nullptr;
+      return BITSORT_ERR_NO_MEMORY;
+    }
+    c.desc_host_bytes = dbytes;
+  }
+  std::memcpy(c.desc_host, p.desc.data(), dbytes);
+  if (hipMemcpyAsync(static_cast<char*>(c.batch_ws) + p.off_desc, c.desc_host, dbytes, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipEventRecord(c.desc_copied, s) != hipSuccess)
+    return BITSORT_ERR_HIP;
+  return run_multi(p, count, c.batch_ws, s);
 }
 
 int bitsort_batch_status(bitsort_stream_t stream, bitsort_status_t* status, uint32_t num_segments) {

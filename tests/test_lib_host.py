@@ -49,6 +49,15 @@ def test_host_argument_checks(lib):
     assert E.bitsort_radix_u32(fake, 100, 32, fake + 4, 0) == E.BITSORT_ERR_INVALID_ARG  # partial overlap
     assert E.bitsort_radix_workspace_bytes(10, 33) == 0
     assert E.bitsort_count_u32(fake, 10, 28, fake + 4096, 0) == E.BITSORT_ERR_INVALID_ARG  # range_bits > 27
+    import numpy as np
+    kp = np.array([fake], dtype=np.uint64)
+    op = np.array([fake + 4096], dtype=np.uint64)
+    nn = np.array([100], dtype=np.uint64)
+    rb = np.array([6], dtype=np.uint8)  # 100 keys cannot be distinct below 2^6
+    assert E.bitsort_batch_ptr_u32(kp.ctypes.data, nn.ctypes.data, rb.ctypes.data, op.ctypes.data, 1, 0) == \
+        E.BITSORT_ERR_TOO_LARGE
+    assert E.bitsort_batch_ptr_u32(kp.ctypes.data, nn.ctypes.data, rb.ctypes.data, op.ctypes.data, 0, 0) == \
+        E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_count_u32(fake, 100, 20, fake + 4, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_i32(fake, 10, 33, fake + 4096, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_radix_i32(fake, 100, fake + 4, 0) == E.BITSORT_ERR_INVALID_ARG
