@@ -363,12 +363,14 @@ int bitsort_tuning_clear(void);
  * seeded keyed permutation of [0, 2^range_bits), the bitsort_generate_u32
  * generator -- and an arrival time.  The loop admits requests in arrival
  * order as launch slots and memory free up, materialises their keys on the
- * device, and sorts them: requests with range_bits <= plain_range_bits
- * together in one segmented launch (at most max_batch_requests requests and,
- * unless one request alone exceeds it, max_batch_keys keys), wider ones one
- * by one through the plain path, whose partition pass reads the keys once
- * however wide the range (the segmented kernel reads a segment once per
- * 2^20-bit slice of its range); up to
+ * device, and sorts them: consecutive requests with range_bits <=
+ * plain_range_bits together in one segmented launch (bitsort_batch_u32's
+ * kernels), consecutive wider requests of fewer than 2^22 keys together in
+ * one pointer-array launch (bitsort_batch_ptr_u32's kernels: the partition
+ * reads every key once however wide the range), and a wider request of 2^22
+ * keys or more alone through the plain path -- a launch takes at most
+ * max_batch_requests requests and, unless one request alone exceeds it,
+ * max_batch_keys keys; up to
  * `streams` launches are in flight at once, each on its own stream.  The
  * memory of a launch (keys, output, workspace) is one region of an arena of
  * budget_bytes, held until the launch finishes.  The arena is the caller's
@@ -411,7 +413,7 @@ typedef struct bitsort_serve_config {
     uint32_t streams;            /* 1 .. 16 */
     uint32_t max_batch_requests; /* >= 1 */
     uint64_t max_batch_keys;     /* >= 1 */
-    uint32_t plain_range_bits;   /* wider requests run alone on the plain path; 0: BITSORT_BATCH_MAX_RANGE_BITS */
+    uint32_t plain_range_bits;   /* narrower requests share segmented launches; 0: 20, at most 24 */
     uint32_t verify;
     uint32_t simulate;
     uint32_t _pad;

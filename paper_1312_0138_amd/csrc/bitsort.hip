@@ -425,6 +425,7 @@ int check_multi_args(const uint32_t* const* keys, const uint64_t* n, const uint8
 // most 4096 slices), tiles of kMultiTile keys.
 void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8_t* range_bits,
                      uint32_t* const* out, uint32_t count, MultiPlan* p) {
+  *p = MultiPlan();
   p->desc.resize(count);
   for (uint32_t a = 0; a < count; ++a) {
     MultiDesc& d = p->desc[a];

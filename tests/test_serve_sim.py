@@ -26,12 +26,28 @@ def test_all_served_and_counted():
     assert np.all(res["launch_s"] >= req["arrival_s"])
 
 
+def _kinds(req, thr=20):
+    """0: segmented launch, 1: pointer-array launch, 2: alone (the loop's rule)."""
+    wide = req["range_bits"] > thr
+    return np.where(~wide, 0, np.where(req["n"] >= 1 << 22, 2, 1))
+
+
 def test_fifo_admission_order():
-    req = _trace(seed=11)
+    req = _trace(count=600, lo=1000, hi=1 << 23, rate=5e4, seed=11)
     res, _ = _run(req, budget=64 << 20, streams=3)
+    kinds = _kinds(req)
+    assert len(set(kinds.tolist())) == 3
     order = np.argsort(req["arrival_s"], kind="stable")
-    assert np.all(np.diff(res["launch_s"][order]) >= 0)
-    assert np.all(np.diff(res["batch"][order].astype(np.int64)) >= 0)
+    order = order[res["flags"][order] == 0]  # rejected requests (larger than the budget) never launch
+    for k in range(3):
+        o = order[kinds[order] == k]  # requests of one kind launch in arrival order
+        assert np.all(np.diff(res["launch_s"][o]) >= 0)
+        assert np.all(np.diff(res["batch"][o].astype(np.int64)) >= 0)
+    # no request is overtaken by a later one of its own kind, and a request
+    # waits at most until every earlier request has been launched or is in
+    # the same launch
+    first_launch_after = np.maximum.accumulate(res["launch_s"][order][::-1])[::-1]
+    assert np.all(res["launch_s"][order] <= first_launch_after + 1e-12)
 
 
 def test_peak_within_budget_and_memory_wait():
@@ -63,14 +79,21 @@ def test_batch_key_cap():
 
 
 def test_plain_range_bits_threshold():
-    req = _trace(count=200, lo=1000, hi=1 << 22, rate=float("inf"), seed=13)
+    req = _trace(count=200, lo=1000, hi=1 << 23, rate=float("inf"), seed=13)
     for thr in (16, 20, 24):
         res, _ = _run(req, plain_range_bits=thr)
         ids, counts = np.unique(res["batch"], return_counts=True)
         size = dict(zip(ids.tolist(), counts.tolist()))
         wide = req["range_bits"] > thr
-        assert all(size[b] == 1 for b in res["batch"][wide].tolist())
+        big = wide & (req["n"] >= 1 << 22)
+        # a launch never mixes narrow and wide requests; big wide ones run alone
+        for b in np.unique(res["batch"]):
+            members = res["batch"] == b
+            assert wide[members].all() or not wide[members].any()
+        assert all(size[b] == 1 for b in res["batch"][big].tolist())
         assert any(size[b] > 1 for b in res["batch"][~wide].tolist())
+        if (wide & ~big).sum() > 1:
+            assert any(size[b] > 1 for b in res["batch"][wide & ~big].tolist())
 
 
 def test_wide_requests_run_alone():
