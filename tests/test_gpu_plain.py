@@ -83,6 +83,33 @@ def test_parity_clustered(o):
     np.testing.assert_array_equal(got, want)
 
 
+def test_parity_clustered_full_size(o):
+    """The clustered workload itself: 2^26 draws, de-duplicated (about 1.7 x 10^7 keys)."""
+    keys = inputs.clustered(1 << 26, 28, inputs.config_seed(2, 1))
+    want, _, _ = o.bitmap_sort(keys, 28)
+    got, st = _gpu_sort(keys, 28)
+    assert st.flags == 0 and st.count == keys.size
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("path", [0, 2])
+@pytest.mark.parametrize("rb,density", [(24, 0.55), (24, 0.8), (24, 0.97), (26, 0.7), (22, 0.999)])
+def test_parity_dense_groups(o, rb, density, path):
+    """Dense but not full words (over 16 keys per word) on both emission routes, so
+    that 64-word groups with more keys than one emission window occur."""
+    import paper_1312_0138_amd as bs
+    n = int(density * (1 << rb)) + 5
+    keys = inputs.distinct_uniform(n, rb, 80 + rb)
+    want, _, _ = o.bitmap_sort(keys, rb)
+    bs.set_tuning(0, 0, path)
+    try:
+        got, st = _gpu_sort(keys, rb)
+    finally:
+        bs.set_tuning(0, 0, 0)
+    assert st.flags == 0 and st.count == n
+    np.testing.assert_array_equal(got, want)
+
+
 def test_dense_permutation_is_identity():
     """A permutation of all of [0, 2^28) sorts to 0, 1, ..., 2^28-1."""
     import torch
