@@ -292,17 +292,20 @@ int bitsort_debug_prefix_u32(const uint32_t *keys, uint64_t n, uint32_t range_bi
  * Tuning knobs for the plain path (0 = library default).
  *   slice_bits  bits of key range per LDS slice (10..20);
  *   tile_log2   keys per partition tile as a power of two (12..15);
- *   emit_path   1: emit each slice from LDS (k_slice); 2: write the bit-vector
- *               to HBM and emit from it at full occupancy (k_slice + k_emit,
- *               needs slice_bits >= 15); 0: choose by size (the HBM bit-vector
- *               when R/8 <= 2n).
+ *   emit_path   1: emit each slice from LDS (k_slice), scanning every word;
+ *               2: write the bit-vector to HBM and emit from it at full
+ *               occupancy (k_slice + k_emit, needs slice_bits >= 15);
+ *               3: emit from LDS through a summary bit per word, reading only
+ *               nonzero words (needs slice_bits = 20);
+ *               0: choose by size (the HBM bit-vector when R/8 <= 2n, the
+ *               summary when n <= R/32 and the slice has 2^20 bits).
  * Affects calls made afterwards in this process.
  */
 int bitsort_set_tuning(uint32_t slice_bits, uint32_t tile_log2, uint32_t emit_path);
 
 /* The slice_bits, tile_log2 (0 for the single-workgroup path), number of
- * slices and emit path (0 single workgroup, 1 LDS, 2 HBM bit-vector) that the
- * plain path would use for (n, range_bits). */
+ * slices and emit path (0 single workgroup, 1 LDS, 2 HBM bit-vector, 3 LDS
+ * through the word summary) that the plain path would use for (n, range_bits). */
 int bitsort_plan_info(uint64_t n, uint32_t range_bits, uint32_t *slice_bits, uint32_t *tile_log2,
                       uint32_t *buckets, uint32_t *emit_path);
 
@@ -343,7 +346,7 @@ int bitsort_graph_destroy(bitsort_graph_t *graph);
 typedef struct bitsort_tuning {
     uint32_t slice_bits;  /* plain and batch */
     uint32_t tile_log2;   /* plain */
-    uint32_t emit_path;   /* plain: 1 LDS, 2 HBM bit-vector */
+    uint32_t emit_path;   /* plain: 1 LDS, 2 HBM bit-vector, 3 LDS with word summary */
     uint32_t batch_block; /* batch: workgroup size */
     float ms;             /* measured time per call */
 } bitsort_tuning_t;

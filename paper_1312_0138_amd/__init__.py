@@ -293,7 +293,7 @@ def set_tuning(slice_bits: int = 0, tile_log2: int = 0, emit_path: int = 0) -> N
     _lib.check(_lib.bitsort_set_tuning(slice_bits, tile_log2, emit_path), "bitsort_set_tuning")
 
 
-EMIT_PATHS = {0: "single-workgroup", 1: "lds", 2: "hbm-bitvector"}
+EMIT_PATHS = {0: "single-workgroup", 1: "lds", 2: "hbm-bitvector", 3: "lds-sparse"}
 
 
 def plan_info(n: int, range_bits: int):

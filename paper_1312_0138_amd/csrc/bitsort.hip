@@ -95,6 +95,7 @@ struct Plan {
   uint32_t rb = 0, sb = 0, nb = 1, tile_log2 = 0, tile_keys = 0, nt = 0;
   bool direct = true;
   bool via_bitvec = false;  // k_slice writes the bit-vector to HBM, k_emit writes the keys
+  bool sparse = false;      // k_slice keeps a summary bit per word and emits only nonzero words
   uint64_t n_chunks = 0;
   size_t off_binfo = 0, off_table = 0, off_staging = 0, off_bitvec = 0, off_chunk = 0, bytes = 0;
   uint32_t stage_cap = 0;
@@ -188,6 +189,12 @@ void make_plan(uint64_t n, uint32_t rb, Plan* p, const PlainTuning* force = null
       p->off_chunk = align256(p->off_bitvec + bv_bytes);
       p->bytes = align256(p->off_chunk + 8ull * p->n_chunks);
     }
+    // About one key per word or fewer: the slice kernel also keeps a summary
+    // bit per word and its emission reads only nonzero words.  Needs the full
+    // 2^20-bit slice, whose 1024 summary words give every lane of the sixteen
+    // waves one.  Path 1 forces the plain word scan, path 3 the summary.
+    if (!p->via_bitvec && sb == kMaxSliceBits && (path == 3 || (path == 0 && 32ull * n <= (1ull << rb))))
+      p->sparse = true;
   }
   p->stage_cap = stage_cap_for(p->sb);
   p->slice_lds = slice_lds_bytes(p->sb, p->stage_cap);
@@ -223,7 +230,8 @@ int init_kernels() {
     set_lds_attr(k_partition<512, 16>, kLdsBytes);
     set_lds_attr(k_partition<1024, 16>, kLdsBytes);
     set_lds_attr(k_partition<1024, 32>, kLdsBytes);
-    set_lds_attr(k_slice<kSliceBlock, kSliceUnroll>, kLdsBytes);
+    set_lds_attr(k_slice<kSliceBlock, kSliceUnroll, false>, kLdsBytes);
+    set_lds_attr(k_slice<kSliceBlock, kSliceUnroll, true>, kLdsBytes);
     set_lds_attr(k_direct<kDirectBlock>, kLdsBytes);
     set_lds_attr(k_count_slice<kSliceBlock, kSliceUnroll>, kLdsBytes);
     set_lds_attr(k_partition_multi, kLdsBytes);
@@ -335,8 +343,9 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
   {
     LaunchTimer timer(kKSlice, stream);
     const uint32_t grid = 8u * ((p.nb + 7u) / 8u);
-    hipLaunchKernelGGL((k_slice<kSliceBlock, kSliceUnroll>), dim3(grid), dim3(kSliceBlock), p.slice_lds, stream,
-                       staging, table, p.nt, p.tile_keys, p.sb, p.nb, p.stage_cap, out, info,
+    auto kernel = p.sparse ? k_slice<kSliceBlock, kSliceUnroll, true> : k_slice<kSliceBlock, kSliceUnroll, false>;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kSliceBlock), p.slice_lds, stream, staging, table, p.nt,
+                       p.tile_keys, p.sb, p.nb, p.stage_cap, out, info,
                        p.via_bitvec ? static_cast<int>(kToBitVector) : mode, dbg_bitmap, dbg_prefix, bitvec,
                        chunk_base, 0u - p.bias);
     rc = launch_status();
@@ -1246,7 +1255,7 @@ int bitsort_autotune_u32(uint64_t n, uint32_t range_bits, int reps, bitsort_stre
   }
   rc = bitsort_generate_u32(keys, 0, n, range_bits, 0x5EEDull + range_bits, stream);
   // Candidates: the five widest slice sizes the fan-out limit allows, every
-  // tile size, both emit paths.
+  // tile size, every emit path (the summary one only where it applies).
   const uint32_t sb_lo = std::max<uint32_t>(kMinSliceBits, range_bits > kMaxBucketsLog2 ? range_bits - kMaxBucketsLog2 : 0);
   const uint32_t sb_hi = std::min(kMaxSliceBits, range_bits);
   void* ws = nullptr;
@@ -1254,11 +1263,12 @@ int bitsort_autotune_u32(uint64_t n, uint32_t range_bits, int reps, bitsort_stre
   float best_ms = 1e30f;
   for (uint32_t sb = std::max(sb_lo, sb_hi >= 4 ? sb_hi - 4 : 0); sb <= sb_hi && rc == BITSORT_OK; ++sb) {
     for (uint32_t tl = 12; tl <= 15 && rc == BITSORT_OK; ++tl) {
-      for (uint32_t path = 1; path <= 2 && rc == BITSORT_OK; ++path) {
+      for (uint32_t path = 1; path <= 3 && rc == BITSORT_OK; ++path) {
         const PlainTuning cand{sb, tl, path, 0.f};
         Plan p;
         make_plan(n, range_bits, &p, &cand);
-        if (p.direct || p.sb != sb || p.tile_log2 != tl || (path == 2) != p.via_bitvec) continue;
+        if (p.direct || p.sb != sb || p.tile_log2 != tl || (path == 2) != p.via_bitvec || (path == 3) != p.sparse)
+          continue;
         rc = grow(&ws, &ws_bytes, p.bytes, s);
         if (rc != BITSORT_OK) break;
         const float ms = time_ms([&] { return run_plain(p, keys, n, out, ws, s, kEmit, nullptr, nullptr); },
@@ -1491,7 +1501,7 @@ int bitsort_profile_read(bitsort_profile_entry_t* entries, int max_entries, int*
 int bitsort_set_tuning(uint32_t slice_bits, uint32_t tile_log2, uint32_t emit_path) {
   if (slice_bits != 0 && (slice_bits < kMinSliceBits || slice_bits > kMaxSliceBits)) return BITSORT_ERR_INVALID_ARG;
   if (tile_log2 != 0 && (tile_log2 < 12 || tile_log2 > 15)) return BITSORT_ERR_INVALID_ARG;
-  if (emit_path > 2) return BITSORT_ERR_INVALID_ARG;
+  if (emit_path > 3) return BITSORT_ERR_INVALID_ARG;
   g_tune_sb.store(slice_bits);
   g_tune_tile.store(tile_log2);
   g_tune_path.store(emit_path);
@@ -1508,7 +1518,7 @@ int bitsort_plan_info(uint64_t n, uint32_t range_bits, uint32_t* slice_bits, uin
   *slice_bits = p.sb;
   *tile_log2 = p.direct ? 0 : p.tile_log2;
   *buckets = p.nb;
-  *emit_path = p.direct ? 0u : (p.via_bitvec ? 2u : 1u);
+  *emit_path = p.direct ? 0u : (p.via_bitvec ? 2u : (p.sparse ? 3u : 1u));
   return BITSORT_OK;
 }
 

@@ -81,7 +81,7 @@ def test_autotune_plain_and_cache(o, tmp_path):
     import paper_1312_0138_amd as bs
     n, rb = 1 << 22, 26
     best = bs.autotune(n, rb, reps=2)
-    assert 10 <= best["slice_bits"] <= 20 and 12 <= best["tile_log2"] <= 15 and best["emit_path"] in (1, 2)
+    assert 10 <= best["slice_bits"] <= 20 and 12 <= best["tile_log2"] <= 15 and best["emit_path"] in (1, 2, 3)
     info = bs.plan_info(n, rb)
     assert info["slice_bits"] == best["slice_bits"] and info["tile_log2"] == best["tile_log2"]
     keys = inputs.distinct_uniform(n, rb, 45)

@@ -182,6 +182,50 @@ def test_both_emit_paths(o, n, rb, path):
     np.testing.assert_array_equal(got, want)
 
 
+# (n, range_bits, forced emit path): 0 lets the library choose (the word summary
+# for n <= R/32 with 2^20-bit slices), 1 forces the plain word scan, 3 the summary.
+SPARSE_CASES = [(1 << 20, 28, 0), (1 << 20, 28, 1), (1_000_003, 30, 0), ((1 << 22) + 17, 32, 0), (5000, 32, 0),
+                (70_001, 26, 3), (1 << 23, 28, 0), ((1 << 23) + 1, 28, 3), (1 << 24, 28, 3)]
+
+
+@pytest.mark.parametrize("n,rb,path", SPARSE_CASES)
+def test_sparse_summary_path(o, n, rb, path):
+    """Emission through the per-word summary (few keys per word) against the oracle,
+    with the plan the test means to exercise."""
+    import paper_1312_0138_amd as bs
+    keys = inputs.distinct_uniform(n, rb, 90 + rb)
+    want, _, _ = o.bitmap_sort(keys, rb)
+    bs.set_tuning(20 if path == 3 else 0, 0, path)  # the summary needs 2^20-bit slices
+    try:
+        plan = bs.plan_info(n, rb)
+        sparse = path == 3 or (path == 0 and 32 * n <= 1 << rb)
+        assert plan["emit_path"] == ("lds-sparse" if sparse else "lds"), plan
+        got, st = _gpu_sort(keys, rb)
+    finally:
+        bs.set_tuning(0, 0, 0)
+    assert st.flags == 0 and st.count == n
+    np.testing.assert_array_equal(got, want)
+
+
+def test_sparse_summary_duplicates_and_range(o):
+    """Duplicates and keys beyond the range on the summary path: flags, count and the
+    compacted output as the oracle gives them."""
+    import paper_1312_0138_amd as bs
+    rb = 30
+    base = inputs.distinct_uniform(300_000, rb, 97)
+    rng = np.random.default_rng(5)
+    dup = rng.choice(base, size=2000, replace=False)
+    bad = (np.uint64(1) << np.uint64(rb)) + rng.integers(0, 1 << 20, size=300).astype(np.uint64)
+    keys = np.concatenate([base, dup, bad.astype(np.uint32)])
+    rng.shuffle(keys)
+    want, _, _ = o.bitmap_sort(keys, rb)
+    assert bs.plan_info(keys.size, rb)["emit_path"] == "lds-sparse"
+    got, st = _gpu_sort(keys, rb)
+    assert st.flags == (bs.STATUS_OUT_OF_RANGE | bs.STATUS_DUPLICATE)
+    assert st.count == want.size
+    np.testing.assert_array_equal(got[:want.size], want)
+
+
 @pytest.mark.parametrize("path", [1, 2])
 def test_duplicates_and_range_on_both_paths(o, path):
     import paper_1312_0138_amd as bs

@@ -40,7 +40,7 @@ def test_host_argument_checks(lib):
     assert E.bitsort_workspace_bytes(10, 33) == 0
     assert E.bitsort_set_tuning(9, 0, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_set_tuning(0, 16, 0) == E.BITSORT_ERR_INVALID_ARG
-    assert E.bitsort_set_tuning(0, 0, 3) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_set_tuning(0, 0, 4) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_batch_u32(fake, fake, 0, fake, fake, 0, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_generate_u32(fake, 10, 1, 3, 0, 0) == E.BITSORT_ERR_TOO_LARGE
     assert E.bitsort_radix_u32(fake, 10, 33, fake + 4096, 0) == E.BITSORT_ERR_INVALID_ARG
@@ -74,7 +74,9 @@ def test_plan_shapes(lib):
     rc, sb, tl, nb, ep = _lib.bitsort_plan_info(1 << 26, 28)
     assert rc == 0 and nb == 1 << (28 - sb) and 10 <= sb <= 20 and ep == 2
     rc, sb, tl, nb, ep = _lib.bitsort_plan_info(1 << 24, 32)
-    assert rc == 0 and sb == 20 and nb == 4096 and ep == 1
+    assert rc == 0 and sb == 20 and nb == 4096 and ep == 3  # 1/8 key per word: the word summary
+    rc, sb, tl, nb, ep = _lib.bitsort_plan_info(1_000_000, 24)
+    assert rc == 0 and sb == 16 and nb == 256 and ep == 1  # 2 keys per word: the plain word scan
     rc, sb, tl, nb, ep = _lib.bitsort_plan_info(100, 10)
     assert rc == 0 and nb == 1 and tl == 0 and ep == 0  # single-workgroup path
     ws = _lib.bitsort_workspace_bytes(1 << 26, 28)
