@@ -96,6 +96,7 @@ struct Plan {
   bool direct = true;
   bool via_bitvec = false;  // k_slice writes the bit-vector to HBM, k_emit writes the keys
   bool sparse = false;      // k_slice keeps a summary bit per word and emits only nonzero words
+  bool short_units = false; // segments of a few keys: k_slice gathers 16-key units, four per load
   uint64_t n_chunks = 0;
   size_t off_binfo = 0, off_table = 0, off_staging = 0, off_bitvec = 0, off_chunk = 0, bytes = 0;
   uint32_t stage_cap = 0;
@@ -195,6 +196,10 @@ void make_plan(uint64_t n, uint32_t rb, Plan* p, const PlainTuning* force = null
     // waves one.  Path 1 forces the plain word scan, path 3 the summary.
     if (!p->via_bitvec && sb == kMaxSliceBits && (path == 3 || (path == 0 && 32ull * n <= (1ull << rb))))
       p->sparse = true;
+    // A tile's segment for one slice holds about tile_keys * 2^sb / R keys
+    // (uniform keys).  At 8 or fewer, 64-key units would leave most lanes of
+    // every load idle and take four times the batches: gather 16-key units.
+    p->short_units = (static_cast<uint64_t>(p->tile_keys) << sb) <= (8ull << rb);
   }
   p->stage_cap = stage_cap_for(p->sb);
   p->slice_lds = slice_lds_bytes(p->sb, p->stage_cap);
@@ -230,8 +235,10 @@ int init_kernels() {
     set_lds_attr(k_partition<512, 16>, kLdsBytes);
     set_lds_attr(k_partition<1024, 16>, kLdsBytes);
     set_lds_attr(k_partition<1024, 32>, kLdsBytes);
-    set_lds_attr(k_slice<kSliceBlock, kSliceUnroll, false>, kLdsBytes);
-    set_lds_attr(k_slice<kSliceBlock, kSliceUnroll, true>, kLdsBytes);
+    set_lds_attr(k_slice<kSliceBlock, kSliceUnroll, false, 64>, kLdsBytes);
+    set_lds_attr(k_slice<kSliceBlock, kSliceUnroll, true, 64>, kLdsBytes);
+    set_lds_attr(k_slice<kSliceBlock, kSliceUnroll, false, 16>, kLdsBytes);
+    set_lds_attr(k_slice<kSliceBlock, kSliceUnroll, true, 16>, kLdsBytes);
     set_lds_attr(k_direct<kDirectBlock>, kLdsBytes);
     set_lds_attr(k_count_slice<kSliceBlock, kSliceUnroll>, kLdsBytes);
     set_lds_attr(k_partition_multi, kLdsBytes);
@@ -343,7 +350,10 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
   {
     LaunchTimer timer(kKSlice, stream);
     const uint32_t grid = 8u * ((p.nb + 7u) / 8u);
-    auto kernel = p.sparse ? k_slice<kSliceBlock, kSliceUnroll, true> : k_slice<kSliceBlock, kSliceUnroll, false>;
+    auto kernel = p.sparse ? (p.short_units ? k_slice<kSliceBlock, kSliceUnroll, true, 16>
+                                            : k_slice<kSliceBlock, kSliceUnroll, true, 64>)
+                           : (p.short_units ? k_slice<kSliceBlock, kSliceUnroll, false, 16>
+                                            : k_slice<kSliceBlock, kSliceUnroll, false, 64>);
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(kSliceBlock), p.slice_lds, stream, staging, table, p.nt,
                        p.tile_keys, p.sb, p.nb, p.stage_cap, out, info,
                        p.via_bitvec ? static_cast<int>(kToBitVector) : mode, dbg_bitmap, dbg_prefix, bitvec,

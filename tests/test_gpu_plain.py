@@ -136,7 +136,7 @@ def test_parity_sparse_full_range(o):
 
 # (n, range_bits, emit path): 0 = library choice, 1 = from LDS, 2 = through the HBM bit-vector
 STEP_CASES = [(3000, 12, 0), (1 << 20, 20, 0), (1_000_000, 24, 1), (1_000_000, 24, 2), (40_000, 27, 0),
-              ((1 << 22) + 3, 24, 0), (1 << 22, 26, 2)]
+              ((1 << 22) + 3, 24, 0), (1 << 22, 26, 2), ((1 << 21) + 5, 30, 0)]
 
 
 @pytest.mark.parametrize("n,rb,path", STEP_CASES)
@@ -184,8 +184,12 @@ def test_both_emit_paths(o, n, rb, path):
 
 # (n, range_bits, forced emit path): 0 lets the library choose (the word summary
 # for n <= R/32 with 2^20-bit slices), 1 forces the plain word scan, 3 the summary.
+# Segments of 8 keys or fewer per tile and slice (2^14 << 20 <= 8 R, or 2^12 << 20
+# <= 8 R) switch the gather to 16-key units: (2^22 + 17, 32), (2^22 + 9, 32, 1),
+# (2^21, 30) and (5000, 32) take them, with and without the summary.
 SPARSE_CASES = [(1 << 20, 28, 0), (1 << 20, 28, 1), (1_000_003, 30, 0), ((1 << 22) + 17, 32, 0), (5000, 32, 0),
-                (70_001, 26, 3), (1 << 23, 28, 0), ((1 << 23) + 1, 28, 3), (1 << 24, 28, 3)]
+                (70_001, 26, 3), (1 << 23, 28, 0), ((1 << 23) + 1, 28, 3), (1 << 24, 28, 3),
+                ((1 << 22) + 9, 32, 1), (1 << 21, 30, 0)]
 
 
 @pytest.mark.parametrize("n,rb,path", SPARSE_CASES)
