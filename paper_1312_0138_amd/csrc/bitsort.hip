@@ -168,7 +168,9 @@ void make_plan(uint64_t n, uint32_t rb, Plan* p, const PlainTuning* force = null
     p->nb = 1u << (rb - sb);
     uint32_t tl = force ? 0u : g_tune_tile.load();
     if (tl == 0) tl = tuned.tile_log2;
-    if (tl == 0) tl = n >= (1ull << 22) ? 14 : 12;
+    // 2^14-key tiles for large inputs; 2^15 when there are 2048 slices or more,
+    // where a tile's segment per slice would otherwise hold only a few keys
+    if (tl == 0) tl = n >= (1ull << 22) ? (p->nb >= 2048 ? 15 : 14) : 12;
     tl = std::min<uint32_t>(std::max<uint32_t>(tl, 12), 15);
     p->tile_log2 = tl;
     p->tile_keys = 1u << tl;
@@ -239,6 +241,8 @@ int init_kernels() {
     set_lds_attr(k_slice<kSliceBlock, kSliceUnroll, true, 64>, kLdsBytes);
     set_lds_attr(k_slice<kSliceBlock, kSliceUnroll, false, 16>, kLdsBytes);
     set_lds_attr(k_slice<kSliceBlock, kSliceUnroll, true, 16>, kLdsBytes);
+    set_lds_attr(k_slice_seq<kSliceBlock, kSliceUnroll, 16>, kLdsBytes);
+    set_lds_attr(k_slice_seq<kSliceBlock, kSliceUnroll, 64>, kLdsBytes);
     set_lds_attr(k_direct<kDirectBlock>, kLdsBytes);
     set_lds_attr(k_count_slice<kSliceBlock, kSliceUnroll>, kLdsBytes);
     set_lds_attr(k_partition_multi, kLdsBytes);
@@ -326,6 +330,19 @@ int launch_partition(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* 
   return launch_status();
 }
 
+// Compute units of the current device (cached per device).
+uint32_t device_cus() {
+  static std::atomic<int> cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256u;
+  int c = cached[dev].load(std::memory_order_relaxed);
+  if (c <= 0) {
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+    cached[dev].store(c, std::memory_order_relaxed);
+  }
+  return static_cast<uint32_t>(c);
+}
+
 int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, void* ws,
               hipStream_t stream, int mode, uint32_t* dbg_bitmap, uint64_t* dbg_prefix) {
   int rc = init_kernels();
@@ -349,6 +366,16 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
   if (p.via_bitvec && mode == kDumpBitmap) bitvec = dbg_bitmap;  // the mark step's bit-vector is the dump
   {
     LaunchTimer timer(kKSlice, stream);
+    const uint32_t cus = device_cus();
+    if (p.sparse && mode == kEmit && p.nb > cus) {
+      // many sparse slices: one workgroup per CU (a multiple of 8), each
+      // taking every (grid/8)-th slice of its XCD's run
+      const uint32_t grid = std::max(8u, cus & ~7u);
+      auto kernel = p.short_units ? k_slice_seq<kSliceBlock, kSliceUnroll, 16> : k_slice_seq<kSliceBlock, kSliceUnroll, 64>;
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(kSliceBlock), p.slice_lds, stream, staging, table, p.nt,
+                         p.tile_keys, p.sb, p.nb, out, info, 0u - p.bias);
+      rc = launch_status();
+    } else {
     const uint32_t grid = 8u * ((p.nb + 7u) / 8u);
     auto kernel = p.sparse ? (p.short_units ? k_slice<kSliceBlock, kSliceUnroll, true, 16>
                                             : k_slice<kSliceBlock, kSliceUnroll, true, 64>)
@@ -359,6 +386,7 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
                        p.via_bitvec ? static_cast<int>(kToBitVector) : mode, dbg_bitmap, dbg_prefix, bitvec,
                        chunk_base, 0u - p.bias);
     rc = launch_status();
+    }
   }
   if (rc != BITSORT_OK || mode == kDumpBitmap || (mode == kDumpPrefix && !p.via_bitvec)) return rc;
   if (p.via_bitvec) {

@@ -211,6 +211,24 @@ def test_sparse_summary_path(o, n, rb, path):
     np.testing.assert_array_equal(got, want)
 
 
+def test_sparse_slices_over_several_rounds_of_tiles(o):
+    """Many sparse slices per workgroup with more than 1024 tiles, so that each slice's
+    gather runs over several rounds of tiles after the prefetched first one."""
+    import paper_1312_0138_amd as bs
+    n, rb = (1 << 22) + 3, 32
+    keys = inputs.distinct_uniform(n, rb, 99)
+    want, _, _ = o.bitmap_sort(keys, rb)
+    bs.set_tuning(0, 12, 0)
+    try:
+        plan = bs.plan_info(n, rb)
+        assert plan["emit_path"] == "lds-sparse" and plan["tile_log2"] == 12 and plan["buckets"] == 4096
+        got, st = _gpu_sort(keys, rb)
+    finally:
+        bs.set_tuning(0, 0, 0)
+    assert st.flags == 0 and st.count == n
+    np.testing.assert_array_equal(got, want)
+
+
 def test_sparse_summary_duplicates_and_range(o):
     """Duplicates and keys beyond the range on the summary path: flags, count and the
     compacted output as the oracle gives them."""
