@@ -637,7 +637,9 @@ struct RadixPlan {
 
 // Items per thread of k_radix_pass: 32 for 32-bit keys alone, 16 when the
 // tile's LDS holds 8-byte keys or keys and values (32 KiB either way).
-constexpr uint32_t radix_items(uint32_t key_bytes, bool pairs) { return key_bytes == 4 && !pairs ? 32u : 16u; }
+// Keys per thread of a radix tile (256 threads): 32 for uint32 keys, 20 for
+// uint64 keys and key-value records (measured over 16..24 and 32..48).
+constexpr uint32_t radix_items(uint32_t key_bytes, bool pairs) { return key_bytes == 4 && !pairs ? 32u : 20u; }
 
 // Workspace: status header, then (cleared by k_radix_hist) one ticket per
 // pass and the look-back words [passes][tiles][256], then the partial
