@@ -606,7 +606,7 @@ def main():
         import paper_1312_0138_amd as bs
         bs.set_tuning(*[int(v) for v in args.tune.split(",")])
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         result = bench_batch(args)
