@@ -44,6 +44,21 @@ def test_random_full_width(o, n):
     assert st.flags == 0 and st.count == n
 
 
+@pytest.mark.parametrize("n", [5, 4099, 100_003])
+def test_unaligned_input(o, n):
+    """Keys starting 4 bytes past a 16-byte boundary (the histogram's scalar path) and
+    sizes with a ragged tail of the 16-byte loads."""
+    import paper_1312_0138_amd as bs
+    keys = _rand(n + 1, 32, 300 + n)
+    base = to_dev(keys)
+    view = base[1:]
+    assert view.data_ptr() % 16 != 0
+    got = to_np(bs.radix_sort(view, 32))
+    np.testing.assert_array_equal(got, o.bitwise_sort1(keys[1:], 32))
+    st = bs.status()
+    assert st.flags == 0 and st.count == n
+
+
 @pytest.mark.parametrize("key_bits", [0, 1, 5, 8, 9, 16, 17, 24, 31])
 def test_key_bits(o, key_bits):
     n = 2 * TILE + 333
@@ -171,6 +186,17 @@ def test_u64_key_bits_and_out_of_range(o, key_bits):
     got = bs.radix_sort_u64(_dev64(keys), key_bits).cpu().numpy().view(np.uint64)
     np.testing.assert_array_equal(got, o.bitwise_sort1_u64(keys, key_bits))
     assert bs.status().flags == (1 if key_bits < 64 else 0)
+
+
+def test_u64_unaligned_input(o):
+    """64-bit keys starting 8 bytes past a 16-byte boundary."""
+    import paper_1312_0138_amd as bs
+    rng = np.random.default_rng(77)
+    keys = rng.integers(0, 1 << 64, size=20_001, dtype=np.uint64)
+    view = _dev64(keys)[1:]
+    assert view.data_ptr() % 16 != 0
+    got = bs.radix_sort_u64(view, 64).cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(got, o.bitwise_sort1_u64(keys[1:], 64))
 
 
 def test_u64_in_place_and_duplicates(o):
