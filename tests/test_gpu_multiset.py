@@ -27,7 +27,7 @@ def _count(keys, rb):
 
 
 @pytest.mark.parametrize("rb,n", [(0, 10), (1, 1000), (5, 64), (10, 4096), (12, 4097), (16, 100_000), (20, 1_000_000),
-                                  (24, 1 << 22), (27, 1 << 20), (27, 12_345)])
+                                  (24, 1 << 22), (27, 1 << 20), (27, 12_345), (12, 131_072), (14, 655_360)])
 def test_random_repeats(o, rb, n):
     rng = np.random.default_rng(rb * 1000 + n)
     keys = rng.integers(0, 1 << rb, size=n, dtype=np.uint64).astype(np.uint32)
