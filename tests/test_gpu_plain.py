@@ -110,6 +110,20 @@ def test_parity_dense_groups(o, rb, density, path):
     np.testing.assert_array_equal(got, want)
 
 
+@pytest.mark.parametrize("n,rb", [(1_000_000, 24), (1 << 24, 26), ((1 << 22) + 17, 32)])
+def test_order_independence(o, n, rb):
+    """Shuffling the input leaves the output unchanged (LDS, bit-vector and summary paths),
+    and the output keeps the invariants: length n, strictly ascending, every key < 2^rb."""
+    keys = inputs.distinct_uniform(n, rb, 101 + rb)
+    got1, st1 = _gpu_sort(keys, rb)
+    shuffled = keys[np.random.default_rng(5).permutation(n)]
+    got2, st2 = _gpu_sort(shuffled, rb)
+    assert st1.flags == st2.flags == 0 and st1.count == st2.count == n
+    np.testing.assert_array_equal(got1, got2)
+    assert got1.size == n and np.all(got1[1:] > got1[:-1]) and int(got1[-1]) < (1 << rb)
+    np.testing.assert_array_equal(got1, o.bitmap_sort(keys, rb)[0])
+
+
 def test_dense_permutation_is_identity():
     """A permutation of all of [0, 2^28) sorts to 0, 1, ..., 2^28-1."""
     import torch
