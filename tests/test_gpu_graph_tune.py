@@ -25,7 +25,7 @@ def o():
     return oracle.default()
 
 
-@pytest.mark.parametrize("n,rb", [(1_000_000, 24), ((1 << 22) + 5, 24), (5000, 16)])
+@pytest.mark.parametrize("n,rb", [(1_000_000, 24), ((1 << 22) + 5, 24), (5000, 16), ((1 << 21) + 3, 32)])
 def test_plain_graph_replays(o, n, rb):
     import torch
     import paper_1312_0138_amd as bs
