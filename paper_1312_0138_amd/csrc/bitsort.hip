@@ -421,7 +421,8 @@ void make_count_plan(uint64_t n, uint32_t rb, Plan* p) {
   p->off_table = align256(p->off_binfo + 24ull * p->nb);
   p->off_staging = align256(p->off_table + 4ull * p->nt * (p->nb + 1));
   p->bytes = align256(p->off_staging + 4ull * p->nt * p->tile_keys);
-  p->slice_lds = 4ull * (64 + (kSliceBlock / kWave) * kWave + (1u << sb));
+  p->slice_lds = 4ull * (64 + (kSliceBlock / kWave) * kWave + (1u << sb) +
+                         (kSliceBlock / kWave) * (kCountWindow + 4u));
 }
 
 int run_count(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, void* ws, hipStream_t stream) {
