@@ -392,6 +392,23 @@ def test_tuning_knobs_keep_results(o, sb, tl, path):
     np.testing.assert_array_equal(got, want)
 
 
+@pytest.mark.parametrize("n,rb,path", [((1 << 24) + 12345, 28, 2), ((1 << 23) + 7, 30, 0), ((1 << 24) + 1, 26, 1)])
+def test_partition_several_tiles_per_workgroup(o, n, rb, path):
+    """2^15-key tiles: one persistent partition workgroup per CU takes several tiles
+    (more than 256 tiles here), the last one ragged."""
+    import paper_1312_0138_amd as bs
+    keys = inputs.distinct_uniform(n, rb, 107 + rb)
+    want, _, _ = o.bitmap_sort(keys, rb)
+    bs.set_tuning(0, 15, path)
+    try:
+        assert bs.plan_info(n, rb)["tile_log2"] == 15
+        got, st = _gpu_sort(keys, rb)
+    finally:
+        bs.set_tuning(0, 0, 0)
+    assert st.flags == 0 and st.count == n
+    np.testing.assert_array_equal(got, want)
+
+
 @pytest.mark.parametrize("rb,first,count", [(0, 0, 1), (1, 0, 2), (5, 3, 20), (7, 0, 128), (16, 100, 5000),
                                             (24, 12345, 100_000), (31, 1 << 30, 70_000), (32, 0, 100_000)])
 def test_device_generator_matches_host(rb, first, count):

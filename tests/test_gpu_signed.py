@@ -55,6 +55,18 @@ def test_bitmap_signed_both_emit_paths(o, emit_path):
     np.testing.assert_array_equal(out, o.bitwise_sort_i32(keys))
 
 
+def test_bitmap_signed_large_tiles(o):
+    """Signed keys through the persistent partition (2^15-key tiles, several per workgroup)."""
+    import paper_1312_0138_amd as bs
+    keys = _signed_distinct((1 << 24) + 3, 28, 78)
+    try:
+        bs.set_tuning(0, 15, 0)
+        out = bs.sort_signed(_dev(keys), 28).cpu().numpy()
+    finally:
+        bs.set_tuning(0, 0, 0)
+    np.testing.assert_array_equal(out, o.bitwise_sort_i32(keys))
+
+
 @pytest.mark.parametrize("rb,n", [(8, 250), (20, 100_000)])
 def test_bitmap_signed_out_of_range_dropped(o, rb, n):
     import paper_1312_0138_amd as bs
