@@ -65,9 +65,10 @@ def test_parity_config_small(o, rep):
     np.testing.assert_array_equal(got, want)
 
 
-def test_parity_config_large_uniform(o):
-    """2^26 distinct keys from [0, 2^28), full size."""
-    keys = inputs.distinct_uniform(1 << 26, 28, inputs.config_seed(2, 0))
+@pytest.mark.parametrize("rep", [0, 1, 2])
+def test_parity_config_large_uniform(o, rep):
+    """2^26 distinct keys from [0, 2^28), full size, three seeds."""
+    keys = inputs.distinct_uniform(1 << 26, 28, inputs.config_seed(2, rep))
     want, _, _ = o.bitmap_sort(keys, 28)
     got, st = _gpu_sort(keys, 28)
     assert st.flags == 0 and st.count == keys.size
@@ -83,9 +84,11 @@ def test_parity_clustered(o):
     np.testing.assert_array_equal(got, want)
 
 
-def test_parity_clustered_full_size(o):
-    """The clustered workload itself: 2^26 draws, de-duplicated (about 1.7 x 10^7 keys)."""
-    keys = inputs.clustered(1 << 26, 28, inputs.config_seed(2, 1))
+@pytest.mark.parametrize("rep", [1, 2, 3])
+def test_parity_clustered_full_size(o, rep):
+    """The clustered workload itself: 2^26 draws, de-duplicated (about 1.7 x 10^7 keys),
+    three seeds."""
+    keys = inputs.clustered(1 << 26, 28, inputs.config_seed(2, rep))
     want, _, _ = o.bitmap_sort(keys, 28)
     got, st = _gpu_sort(keys, 28)
     assert st.flags == 0 and st.count == keys.size
@@ -139,9 +142,10 @@ def test_dense_permutation_is_identity():
     assert torch.equal(out, ref)
 
 
-def test_parity_sparse_full_range(o):
-    """2^24 distinct keys over all of [0, 2^32)."""
-    keys = inputs.distinct_uniform(1 << 24, 32, inputs.config_seed(3, 1))
+@pytest.mark.parametrize("rep", [0, 1, 2])
+def test_parity_sparse_full_range(o, rep):
+    """2^24 distinct keys over all of [0, 2^32), three seeds."""
+    keys = inputs.distinct_uniform(1 << 24, 32, inputs.config_seed(3, rep))
     want, _, _ = o.bitmap_sort(keys, 32)
     got, st = _gpu_sort(keys, 32)
     assert st.flags == 0 and st.count == keys.size
@@ -354,7 +358,7 @@ def test_deterministic_repeats():
     import paper_1312_0138_amd as bs
     keys = to_dev(inputs.distinct_uniform(1 << 22, 26, 13))
     ref = bs.sort(keys, 26).clone()
-    for _ in range(5):
+    for _ in range(10):
         assert torch.equal(bs.sort(keys, 26), ref)
 
 
