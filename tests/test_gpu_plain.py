@@ -55,6 +55,30 @@ def test_parity_sizes(o, n, rb):
     np.testing.assert_array_equal(got, want)
 
 
+@pytest.mark.parametrize("rb", [0, 1, 4, 5, 6, 20, 21, 28, 32])
+@pytest.mark.parametrize("path", [0, 1])
+def test_edge_keys(o, rb, path):
+    """Word, slice and range boundaries: 0, 31, 32, 63, 64, a fully set word (96..127),
+    2^20 - 1 and 2^20 (a slice boundary), R - 1 (the last key, 0xFFFFFFFF at 32 bits),
+    and every key of the range when it is below one word."""
+    import paper_1312_0138_amd as bs
+    R = 1 << rb
+    if rb <= 5:
+        keys = np.arange(R, dtype=np.uint64)
+    else:
+        cand = [0, 31, 32, 63, 64, *range(96, 128), (1 << 20) - 1, 1 << 20, R - 1, R - 2, R // 2]
+        keys = np.array(sorted({c for c in cand if c < R}), dtype=np.uint64)
+    keys = keys.astype(np.uint32)[np.random.default_rng(rb).permutation(keys.size)]
+    want, _, _ = o.bitmap_sort(keys, rb)
+    bs.set_tuning(0, 0, path)
+    try:
+        got, st = _gpu_sort(keys, rb)
+    finally:
+        bs.set_tuning(0, 0, 0)
+    assert st.flags == 0 and st.count == keys.size
+    np.testing.assert_array_equal(got, want)
+
+
 @pytest.mark.parametrize("rep", [0, 1, 2])
 def test_parity_config_small(o, rep):
     """10^6 distinct keys from [0, 2^24), three seeds."""
