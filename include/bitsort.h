@@ -152,10 +152,13 @@ int bitsort_batch_status(bitsort_stream_t stream, bitsort_status_t *status, uint
 
 /*
  * Pointer-array batch: count independent arrays, each sorted by the plain
- * path's method (partition into LDS slices, mark, scan, emit from LDS), all
- * arrays in one launch of each kernel -- any range_bits up to 32 per array,
- * and every key read once by the partition (the segmented launch above reads
- * a segment once per 2^20-bit slice of its range).
+ * path's method (partition into LDS slices, mark, scan, emit), all arrays in
+ * one launch of each kernel -- any range_bits up to 32 per array, and every
+ * key read once by the partition (the segmented launch above reads a segment
+ * once per 2^20-bit slice of its range).  An array emits from LDS, or, when
+ * range_bits >= 21 and its bit-vector is at most twice its keys' bytes
+ * (2^range_bits / 8 <= 2 n), through a bit-vector in the workspace and one
+ * more launch that emits every such array's words.
  *
  *   keys, out    host arrays of count device pointers; array a is keys[a][0 ..
  *                n[a]) and its result goes to out[a][0 .. n[a]).  out[a] ==

@@ -262,12 +262,13 @@ int launch_status() {
 // Kernel timing (bitsort_profile_*): events bracketing each launch.
 enum KernelId : int {
   kKPartition = 0, kKSlice, kKEmit, kKFinish, kKDirect, kKBatchPlan, kKBatchRun, kKRadixHist, kKRadixScan,
-  kKRadixPass, kKCountSlice, kKPartitionMulti, kKSliceMulti, kKFinishMulti, kKCount
+  kKRadixPass, kKCountSlice, kKPartitionMulti, kKSliceMulti, kKEmitMulti, kKFinishMulti, kKCount
 };
 const char* const kKernelNames[kKCount] = {"k_partition", "k_slice",      "k_emit",       "k_finish",
                                            "k_direct",    "k_batch_plan", "k_batch_run",  "k_radix_hist",
                                            "k_radix_scan", "k_radix_pass", "k_count_slice",
-                                           "k_partition_multi", "k_slice_multi", "k_finish_multi"};
+                                           "k_partition_multi", "k_slice_multi", "k_emit_multi",
+                                           "k_finish_multi"};
 struct PendingTiming {
   int kernel;
   hipEvent_t start, stop;
@@ -449,12 +450,13 @@ int run_count(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
 // ---- many arrays through the plain path in one launch per kernel -------------
 
 // Workspace of a multi launch: [header][status x count][descriptors]
-// [slice info][tile tables][staging].
+// [slice info][tile tables][staging][bit-vectors][chunk prefixes].
 struct MultiPlan {
   std::vector<MultiDesc> desc;
-  uint32_t tiles = 0, slices = 0, max_nb = 1, max_sb = kMinSliceBits;
-  uint64_t table_words = 0;
-  size_t off_status = 0, off_desc = 0, off_info = 0, off_table = 0, off_staging = 0, bytes = 0;
+  uint32_t tiles = 0, slices = 0, chunks = 0, max_nb = 1, max_sb = kMinSliceBits;
+  uint64_t table_words = 0, bitvec_words = 0;
+  size_t off_status = 0, off_desc = 0, off_info = 0, off_table = 0, off_staging = 0, off_bitvec = 0, off_chunk = 0,
+         bytes = 0;
 };
 
 int check_multi_args(const uint32_t* const* keys, const uint64_t* n, const uint8_t* range_bits,
@@ -470,7 +472,10 @@ int check_multi_args(const uint32_t* const* keys, const uint64_t* n, const uint8
 }
 
 // Per array: slices of 2^sb bits aiming at 256 slices (sb in [10, 20], at
-// most 4096 slices), tiles of kMultiTile keys.
+// most 4096 slices), tiles of kMultiTile keys.  A range of 2^21 or more whose
+// bit-vector is at most twice the keys' bytes (R/8 <= 2n) emits through the
+// HBM bit-vector, as on the single-array path; its slices are then at least
+// one emission chunk (2^15 bits) wide.
 void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8_t* range_bits,
                      uint32_t* const* out, uint32_t count, MultiPlan* p) {
   *p = MultiPlan();
@@ -481,6 +486,9 @@ void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8
     uint32_t sb = rb > 8 ? rb - 8 : rb;
     sb = std::max({sb, kMinSliceBits, rb > kMaxBucketsLog2 ? rb - kMaxBucketsLog2 : 0u});
     sb = std::min(sb, kMaxSliceBits);
+    const uint64_t bv_bytes = (1ull << rb) / 8u;
+    d.via_bitvec = (rb >= 21 && bv_bytes <= 2 * n[a]) ? 1u : 0u;
+    if (d.via_bitvec) sb = std::max<uint32_t>(sb, kChunkLog2Bits);
     d.keys = keys[a];
     d.out = out[a];
     d.n = n[a];
@@ -494,6 +502,12 @@ void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8
     p->tiles += d.nt;
     p->slices += d.nb;
     p->table_words += static_cast<uint64_t>(d.nt) * (d.nb + 1);
+    d.chunk0 = p->chunks;
+    d.bitvec_off = p->bitvec_words;
+    if (d.via_bitvec) {
+      p->chunks += 1u << (rb - kChunkLog2Bits);
+      p->bitvec_words += 1ull << (rb - 5);
+    }
     p->max_nb = std::max(p->max_nb, d.nb);
     p->max_sb = std::max(p->max_sb, d.sb);
   }
@@ -508,6 +522,10 @@ void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8
   o = align256(o + 4ull * p->table_words);
   p->off_staging = o;
   o = align256(o + 4ull * p->tiles * kMultiTile);
+  p->off_bitvec = o;
+  o = align256(o + 4ull * p->bitvec_words);
+  p->off_chunk = o;
+  o = align256(o + 8ull * p->chunks);
   p->bytes = o;
 }
 
@@ -534,7 +552,15 @@ int run_multi(const MultiPlan& p, uint32_t count, void* ws, hipStream_t stream) 
     const uint32_t grid = 8u * ((p.slices + 7u) / 8u);
     hipLaunchKernelGGL((k_slice_multi<kSliceBlock, kSliceUnroll>), dim3(grid), dim3(kSliceBlock),
                        slice_lds_bytes(p.max_sb, stage_cap), stream, desc, count, p.slices, staging, table, info,
-                       stage_cap);
+                       stage_cap, reinterpret_cast<uint32_t*>(base + p.off_bitvec),
+                       reinterpret_cast<uint64_t*>(base + p.off_chunk));
+    if ((rc = launch_status()) != BITSORT_OK) return rc;
+  }
+  if (p.chunks > 0) {
+    LaunchTimer timer(kKEmitMulti, stream);
+    hipLaunchKernelGGL(k_emit_multi<kEmitBlock>, dim3(p.chunks), dim3(kEmitBlock), 0, stream, desc, count,
+                       reinterpret_cast<const uint32_t*>(base + p.off_bitvec),
+                       reinterpret_cast<const uint64_t*>(base + p.off_chunk));
     if ((rc = launch_status()) != BITSORT_OK) return rc;
   }
   LaunchTimer timer(kKFinishMulti, stream);

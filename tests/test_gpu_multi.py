@@ -83,3 +83,23 @@ def test_wide_segments_match_batch_kernel():
     views = [k[int(offsets[i]):int(offsets[i + 1])] for i in range(64)]
     outs = bs.sort_many(views, [int(r) for r in rbits])
     assert torch.equal(torch.cat(outs), ref)
+
+
+def test_bitvector_route(o):
+    # arrays with R/8 <= 2n and R >= 2^21 emit through the HBM bit-vector;
+    # they sit between LDS-emitting arrays so that the chunk search skips
+    # arrays without chunks
+    spec = [(1 << 17, 21), (3000, 14), ((1 << 20) + 77, 24), (1 << 21, 21), (0, 22), ((1 << 22) - 3, 24),
+            (100_000, 23), ((1 << 19) + 1, 23), (9, 4)]
+    arrays = [inputs.distinct_uniform(n, rb, 500 + i) for i, (n, rb) in enumerate(spec)]
+    _check(o, arrays, [rb for _, rb in spec])
+
+
+def test_bitvector_route_duplicates_and_range(o):
+    rng = np.random.default_rng(8)
+    a = rng.integers(0, 1 << 21, size=1 << 18, dtype=np.uint64).astype(np.uint32)   # repeats
+    b = inputs.distinct_uniform(1 << 19, 23, 4)
+    b[12345] = np.uint32(1 << 23) + 7                                                # out of range
+    c = inputs.dense_permutation(22, 6)
+    c[777] = c[778]                                                                  # one repeat
+    _check(o, [a, b, c], [21, 23, 22])
