@@ -245,7 +245,8 @@ int init_kernels() {
     set_lds_attr(k_slice_seq<kSliceBlock, kSliceUnroll, 64>, kLdsBytes);
     set_lds_attr(k_direct<kDirectBlock>, kLdsBytes);
     set_lds_attr(k_count_slice<kSliceBlock, kSliceUnroll>, kLdsBytes);
-    set_lds_attr(k_partition_multi, kLdsBytes);
+    set_lds_attr(k_partition_multi<256>, kLdsBytes);
+    set_lds_attr(k_partition_multi<1024>, kLdsBytes);
     set_lds_attr(k_slice_multi<kSliceBlock, kSliceUnroll>, kLdsBytes);
     set_lds_attr(k_batch_run<256>, kLdsBytes);
     set_lds_attr(k_batch_run<512>, kLdsBytes);
@@ -453,7 +454,7 @@ int run_count(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
 // [slice info][tile tables][staging][bit-vectors][chunk prefixes].
 struct MultiPlan {
   std::vector<MultiDesc> desc;
-  uint32_t tiles = 0, slices = 0, chunks = 0, max_nb = 1, max_sb = kMinSliceBits;
+  uint32_t tiles = 0, slices = 0, chunks = 0, max_nb = 1, max_sb = kMinSliceBits, tile_log2 = 12;
   uint64_t table_words = 0, bitvec_words = 0;
   size_t off_status = 0, off_desc = 0, off_info = 0, off_table = 0, off_staging = 0, off_bitvec = 0, off_chunk = 0,
          bytes = 0;
@@ -472,7 +473,7 @@ int check_multi_args(const uint32_t* const* keys, const uint64_t* n, const uint8
 }
 
 // Per array: slices of 2^sb bits aiming at 256 slices (sb in [10, 20], at
-// most 4096 slices), tiles of kMultiTile keys.  A range of 2^21 or more whose
+// most 4096 slices), tiles of 2^tile_log2 keys.  A range of 2^21 or more whose
 // bit-vector is at most twice the keys' bytes (R/8 <= 2n) emits through the
 // HBM bit-vector, as on the single-array path; its slices are then at least
 // one emission chunk (2^15 bits) wide.
@@ -480,6 +481,10 @@ void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8
                      uint32_t* const* out, uint32_t count, MultiPlan* p) {
   *p = MultiPlan();
   p->desc.resize(count);
+  uint64_t total = 0;
+  for (uint32_t a = 0; a < count; ++a) total += n[a];
+  p->tile_log2 = total >= (static_cast<uint64_t>(count) << 16) ? 14u : 12u;
+  const uint64_t tile_keys = 1ull << p->tile_log2;
   for (uint32_t a = 0; a < count; ++a) {
     MultiDesc& d = p->desc[a];
     const uint32_t rb = range_bits[a];
@@ -495,7 +500,7 @@ void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8
     d.rb = rb;
     d.sb = sb;
     d.nb = rb > sb ? 1u << (rb - sb) : 1u;
-    d.nt = static_cast<uint32_t>((n[a] + kMultiTile - 1) / kMultiTile);
+    d.nt = static_cast<uint32_t>((n[a] + tile_keys - 1) / tile_keys);
     d.tile0 = p->tiles;
     d.slice0 = p->slices;
     d.table_off = p->table_words;
@@ -521,7 +526,7 @@ void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8
   p->off_table = o;
   o = align256(o + 4ull * p->table_words);
   p->off_staging = o;
-  o = align256(o + 4ull * p->tiles * kMultiTile);
+  o = align256(o + 4ull * p->tiles * tile_keys);
   p->off_bitvec = o;
   o = align256(o + 4ull * p->bitvec_words);
   p->off_chunk = o;
@@ -541,9 +546,13 @@ int run_multi(const MultiPlan& p, uint32_t count, void* ws, hipStream_t stream) 
   uint32_t* staging = reinterpret_cast<uint32_t*>(base + p.off_staging);
   if (p.tiles > 0) {
     LaunchTimer timer(kKPartitionMulti, stream);
-    const size_t part_lds = 4ull * (32 + round_up4(p.max_nb) + kMultiTile);
-    hipLaunchKernelGGL(k_partition_multi, dim3(p.tiles), dim3(kMultiBlock), part_lds, stream, desc, count, staging,
-                       table);
+    const size_t part_lds = 4ull * (32 + round_up4(p.max_nb) + (1u << p.tile_log2));
+    if (p.tile_log2 == 14)
+      hipLaunchKernelGGL(k_partition_multi<1024>, dim3(p.tiles), dim3(1024), part_lds, stream, desc, count, staging,
+                         table);
+    else
+      hipLaunchKernelGGL(k_partition_multi<256>, dim3(p.tiles), dim3(256), part_lds, stream, desc, count, staging,
+                         table);
     if ((rc = launch_status()) != BITSORT_OK) return rc;
   }
   {
@@ -551,7 +560,8 @@ int run_multi(const MultiPlan& p, uint32_t count, void* ws, hipStream_t stream) 
     const uint32_t stage_cap = stage_cap_for(p.max_sb);
     const uint32_t grid = 8u * ((p.slices + 7u) / 8u);
     hipLaunchKernelGGL((k_slice_multi<kSliceBlock, kSliceUnroll>), dim3(grid), dim3(kSliceBlock),
-                       slice_lds_bytes(p.max_sb, stage_cap), stream, desc, count, p.slices, staging, table, info,
+                       slice_lds_bytes(p.max_sb, stage_cap), stream, desc, count, p.slices, 1u << p.tile_log2,
+                       staging, table, info,
                        stage_cap, reinterpret_cast<uint32_t*>(base + p.off_bitvec),
                        reinterpret_cast<uint64_t*>(base + p.off_chunk));
     if ((rc = launch_status()) != BITSORT_OK) return rc;
