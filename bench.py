@@ -434,15 +434,29 @@ def bench_batch(args):
         for k, o, rb in views:
             bs.sort(k, rb, o)
 
+    # the same segments as separate arrays through the pointer-array batch
+    # (bitsort_batch_ptr_u32), its pointer arrays built once on the host
+    out_m = torch.empty_like(keys)
+    kp = (keys.data_ptr() + 4 * offsets[:-1]).astype(np.uint64)
+    op = (out_m.data_ptr() + 4 * offsets[:-1]).astype(np.uint64)
+    nn = sizes.astype(np.uint64)
+    sid = int(stream.cuda_stream)
+
+    def run_pointer_array():
+        _lib.check(_lib.bitsort_batch_ptr_u32(kp.ctypes.data, nn.ctypes.data, rbits.ctypes.data, op.ctypes.data,
+                                              count, sid), "bitsort_batch_ptr_u32")
+
     if args.autotune:
         res_tune = bs.autotune_batch(keys, off_d, rb_d, out_b, reps=2)
     for _ in range(args.warmup):
         run_batch()
         run_graph()
         run_plain()
+        run_pointer_array()
     torch.cuda.synchronize()
     res = {}
-    for name, fn in (("batched", run_batch), ("batched_graph", run_graph), ("plain_loop", run_plain)):
+    for name, fn in (("batched", run_batch), ("batched_graph", run_graph), ("plain_loop", run_plain),
+                     ("pointer_array", run_pointer_array)):
         times = []
         for _ in range(max(3, args.steps // 10)):
             a = torch.cuda.Event(enable_timing=True)
@@ -456,9 +470,9 @@ def bench_batch(args):
         med = times[len(times) // 2]
         res[name] = {"median_ms": round(med, 4), "p99_ms": round(times[-1], 4),
                      "gkeys_per_s": round(total / (med / 1e3) / 1e9, 3)}
-    flags, counts = bs.batch_status(count)
+    flags, counts = bs.batch_status(count)  # of the last call: the pointer-array batch
     assert not flags.any() and np.array_equal(counts, sizes.astype(np.uint64))
-    same = torch.equal(out_b, out_p) and torch.equal(out_g, out_p)
+    same = torch.equal(out_b, out_p) and torch.equal(out_g, out_p) and torch.equal(out_m, out_p)
     ab = sum(4 * int(n) + (1 << int(r)) // 8 + 4 * int(n) for n, r in zip(sizes, rbits))
     med_s = res["batched"]["median_ms"] / 1e3
     return {
@@ -468,6 +482,7 @@ def bench_batch(args):
         "config": {"workload": "batch", "segments": count, "total_keys": total,
                    "sizes": "log-uniform in [256, 2^20]", "range": "next power of two >= 4n"},
         "batched": res["batched"], "batched_graph": res["batched_graph"], "plain_loop": res["plain_loop"],
+        "pointer_array": res["pointer_array"],
         "autotuned": res_tune if args.autotune else None,
         "batched_over_plain": round(res["plain_loop"]["median_ms"] / res["batched"]["median_ms"], 3),
         "identical_results": bool(same),

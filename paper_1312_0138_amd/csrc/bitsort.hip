@@ -472,14 +472,15 @@ int check_multi_args(const uint32_t* const* keys, const uint64_t* n, const uint8
   return BITSORT_OK;
 }
 
-// Per array: slices of 2^sb bits aiming at 256 slices (sb in [10, 20], at
-// most 4096 slices), tiles of 2^tile_log2 keys.  A range of 2^21 or more whose
+// Per array: 2^split slices of 2^sb bits (sb in [10, 20], at most 4096
+// slices), tiles of 2^tile_log2 keys.  split is set per launch, the smallest
+// of 0..8 that gives the launch 512 slices or more (two per CU): few wide
+// slices mean few table rows to walk and little fixed cost per key, as on the
+// single-array path with its 2^20-bit slices.  A range of 2^21 or more whose
 // bit-vector is at most twice the keys' bytes (R/8 <= 2n) emits through the
-// HBM bit-vector, as on the single-array path.  Its slices are at least one
-// emission chunk (2^15 bits) wide and as wide as the launch allows: 2^bv_split
-// of them per array, bv_split the smallest of 4..8 that gives the launch 512
-// slices or more (two per CU).  Few wide slices mean few table rows to walk
-// per key; the single-array path likewise uses 2^20-bit slices.
+// HBM bit-vector, as on the single-array path; such an array takes a split of
+// 4 or more (measured best) and slices of at least one emission chunk (2^15
+// bits).
 void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8_t* range_bits,
                      uint32_t* const* out, uint32_t count, MultiPlan* p) {
   *p = MultiPlan();
@@ -492,18 +493,18 @@ void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8
     const uint32_t rb = range_bits[a];
     return rb >= 21 && (1ull << rb) / 8u <= 2 * n[a];
   };
-  auto slice_bits = [&](uint32_t a, uint32_t bv_split) {
+  auto slice_bits = [&](uint32_t a, uint32_t split) {
     const uint32_t rb = range_bits[a];
-    uint32_t sb = rb > 8 ? rb - 8 : rb;
-    if (via_bitvec(a)) sb = std::max(rb - bv_split, kChunkLog2Bits);
+    uint32_t sb = rb > split ? rb - split : 0u;
+    if (via_bitvec(a)) sb = std::max(rb - std::max(split, 4u), kChunkLog2Bits);
     sb = std::max({sb, kMinSliceBits, rb > kMaxBucketsLog2 ? rb - kMaxBucketsLog2 : 0u});
     return std::min(sb, kMaxSliceBits);
   };
-  uint32_t bv_split = 4;
-  for (; bv_split < 8; ++bv_split) {
+  uint32_t split = 0;
+  for (; split < 8; ++split) {
     uint64_t slices = 0;
     for (uint32_t a = 0; a < count; ++a) {
-      const uint32_t sb = slice_bits(a, bv_split);
+      const uint32_t sb = slice_bits(a, split);
       slices += range_bits[a] > sb ? 1ull << (range_bits[a] - sb) : 1u;
     }
     if (slices >= 512) break;
@@ -511,7 +512,7 @@ void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8
   for (uint32_t a = 0; a < count; ++a) {
     MultiDesc& d = p->desc[a];
     const uint32_t rb = range_bits[a];
-    const uint32_t sb = slice_bits(a, bv_split);
+    const uint32_t sb = slice_bits(a, split);
     d.via_bitvec = via_bitvec(a) ? 1u : 0u;
     d.keys = keys[a];
     d.out = out[a];
