@@ -474,9 +474,12 @@ int check_multi_args(const uint32_t* const* keys, const uint64_t* n, const uint8
 
 // Per array: 2^split slices of 2^sb bits (sb in [10, 20], at most 4096
 // slices), tiles of 2^tile_log2 keys.  split is set per launch, the smallest
-// of 0..8 that gives the launch 512 slices or more (two per CU): few wide
+// of 0..8 that gives the launch 256 slices or more (one per CU): few wide
 // slices mean few table rows to walk and little fixed cost per key, as on the
-// single-array path with its 2^20-bit slices.  A range of 2^21 or more whose
+// single-array path with its 2^20-bit slices.  Tiles hold 2^14 keys when the
+// arrays have 64 slices or more on average (weighted by keys), so that a
+// tile's run of keys per slice stays long, and 2^12 otherwise, where the
+// smaller workgroups partition faster.  A range of 2^21 or more whose
 // bit-vector is at most twice the keys' bytes (R/8 <= 2n) emits through the
 // HBM bit-vector, as on the single-array path; such an array takes a split of
 // 4 or more (measured best) and slices of at least one emission chunk (2^15
@@ -485,10 +488,6 @@ void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8
                      uint32_t* const* out, uint32_t count, MultiPlan* p) {
   *p = MultiPlan();
   p->desc.resize(count);
-  uint64_t total = 0;
-  for (uint32_t a = 0; a < count; ++a) total += n[a];
-  p->tile_log2 = total >= (static_cast<uint64_t>(count) << 16) ? 14u : 12u;
-  const uint64_t tile_keys = 1ull << p->tile_log2;
   auto via_bitvec = [&](uint32_t a) {
     const uint32_t rb = range_bits[a];
     return rb >= 21 && (1ull << rb) / 8u <= 2 * n[a];
@@ -507,8 +506,16 @@ void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8
       const uint32_t sb = slice_bits(a, split);
       slices += range_bits[a] > sb ? 1ull << (range_bits[a] - sb) : 1u;
     }
-    if (slices >= 512) break;
+    if (slices >= 256) break;
   }
+  uint64_t total = 0, weighted = 0;
+  for (uint32_t a = 0; a < count; ++a) {
+    const uint32_t sb = slice_bits(a, split);
+    total += n[a];
+    weighted += n[a] << (range_bits[a] > sb ? range_bits[a] - sb : 0u);
+  }
+  p->tile_log2 = weighted >= 64 * total && total > 0 ? 14u : 12u;
+  const uint64_t tile_keys = 1ull << p->tile_log2;
   for (uint32_t a = 0; a < count; ++a) {
     MultiDesc& d = p->desc[a];
     const uint32_t rb = range_bits[a];
