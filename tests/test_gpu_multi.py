@@ -103,3 +103,15 @@ def test_bitvector_route_duplicates_and_range(o):
     c = inputs.dense_permutation(22, 6)
     c[777] = c[778]                                                                  # one repeat
     _check(o, [a, b, c], [21, 23, 22])
+
+
+def test_bitvector_route_in_place_and_same_as_plain():
+    # out[a] == keys[a] on the bit-vector route, next to an LDS-emitting array
+    import torch
+    import paper_1312_0138_amd as bs
+    spec = ((1 << 20, 22), ((1 << 21) + 5, 23), (40_000, 20))
+    dev = [to_dev(inputs.distinct_uniform(n, rb, 31 + n)) for n, rb in spec]
+    plain = [bs.sort(d, rb) for d, (_, rb) in zip(dev, spec)]
+    bs.sort_many(dev, [rb for _, rb in spec], outs=dev)
+    for d, p in zip(dev, plain):
+        assert torch.equal(d, p)
