@@ -73,6 +73,7 @@ KERNEL_SOURCES = {
     "plain": ["bitsort_device.h", "plain_kernels.inc"],
     "batch": ["bitsort_device.h", "plain_kernels.inc", "batch_kernels.inc"],
     "radix": ["bitsort_device.h", "radix_kernels.inc"],
+    "count": ["bitsort_device.h", "plain_kernels.inc", "count_kernels.inc"],
 }
 
 
@@ -340,7 +341,7 @@ def bench_plain(args, workload):
     kernels = {k: {"launches": int(l), "avg_us": round(1e3 * ms / max(l, 1), 3)} for k, (l, ms) in prof.items()}
     dom = max(prof, key=lambda k: prof[k][1])
     dom_avg_s = prof[dom][1] / prof[dom][0] / 1e3
-    digest = source_digest("radix" if radix else "plain")
+    digest = source_digest("radix" if radix else ("count" if sorter == "count" else "plain"))
     achieved = ab[dom] / dom_avg_s / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
