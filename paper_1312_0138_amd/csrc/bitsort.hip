@@ -1090,8 +1090,8 @@ int bitsort_generate_u32(uint32_t* out, uint64_t first, uint64_t count, uint32_t
   if (count == 0) return BITSORT_OK;
   uint32_t k[4];
   splitmix_keys(seed, k);
-  const uint64_t blocks = std::min<uint64_t>((count + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_generate, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0,
+  const uint64_t blocks = (count + kGenChunk - 1) / kGenChunk;  // count <= 2^32: at most 2^20 blocks
+  hipLaunchKernelGGL(k_generate, dim3(static_cast<uint32_t>(blocks)), dim3(kGenBlock), 0,
                      static_cast<hipStream_t>(stream), out, first, count, range_bits, k[0], k[1], k[2], k[3]);
   return launch_status();
 }
