@@ -115,3 +115,20 @@ def test_bitvector_route_in_place_and_same_as_plain():
     bs.sort_many(dev, [rb for _, rb in spec], outs=dev)
     for d, p in zip(dev, plain):
         assert torch.equal(d, p)
+
+
+def test_batch_workload_shape_matches_segmented_kernel():
+    # sizes log-uniform in [256, 2^20], range the power of two >= 4n: enough
+    # arrays that each takes a single slice unless it is on the bit-vector
+    # route; the segmented kernel sorts the same segments
+    import torch
+    import paper_1312_0138_amd as bs
+    keys, offsets, rbits = inputs.batch_segments(256, 256, 1 << 20, 21)
+    k = to_dev(keys)
+    off = torch.from_numpy(offsets.astype(np.int64)).cuda()
+    ref = bs.sort_batch(k, off, torch.from_numpy(rbits).cuda())
+    views = [k[int(offsets[i]):int(offsets[i + 1])] for i in range(256)]
+    outs = bs.sort_many(views, [int(r) for r in rbits])
+    flags, counts = bs.batch_status(256)
+    assert not flags.any() and np.array_equal(counts, np.diff(offsets).astype(np.uint64))
+    assert torch.equal(torch.cat(outs), ref)
