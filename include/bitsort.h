@@ -371,9 +371,9 @@ int bitsort_tuning_clear(void);
  * order as launch slots and memory free up, materialises their keys on the
  * device, and sorts them: consecutive requests with range_bits <=
  * plain_range_bits together in one segmented launch (bitsort_batch_u32's
- * kernels), consecutive wider requests of fewer than 2^22 keys together in
+ * kernels), consecutive wider requests of fewer than 2^23 keys together in
  * one pointer-array launch (bitsort_batch_ptr_u32's kernels: the partition
- * reads every key once however wide the range), and a wider request of 2^22
+ * reads every key once however wide the range), and a wider request of 2^23
  * keys or more alone through the plain path -- a launch takes at most
  * max_batch_requests requests and, unless one request alone exceeds it,
  * max_batch_keys keys; up to

@@ -29,12 +29,12 @@ def test_all_served_and_counted():
 def _kinds(req, thr=20):
     """0: segmented launch, 1: pointer-array launch, 2: alone (the loop's rule)."""
     wide = req["range_bits"] > thr
-    return np.where(~wide, 0, np.where(req["n"] >= 1 << 22, 2, 1))
+    return np.where(~wide, 0, np.where(req["n"] >= 1 << 23, 2, 1))
 
 
 def test_fifo_admission_order():
-    req = _trace(count=600, lo=1000, hi=1 << 23, rate=5e4, seed=11)
-    res, _ = _run(req, budget=64 << 20, streams=3)
+    req = _trace(count=600, lo=1000, hi=1 << 24, rate=5e4, seed=11)
+    res, _ = _run(req, budget=160 << 20, streams=3)
     kinds = _kinds(req)
     assert len(set(kinds.tolist())) == 3
     order = np.argsort(req["arrival_s"], kind="stable")
@@ -79,13 +79,13 @@ def test_batch_key_cap():
 
 
 def test_plain_range_bits_threshold():
-    req = _trace(count=200, lo=1000, hi=1 << 23, rate=float("inf"), seed=13)
+    req = _trace(count=200, lo=1000, hi=1 << 24, rate=float("inf"), seed=13)
     for thr in (16, 20, 24):
         res, _ = _run(req, plain_range_bits=thr)
         ids, counts = np.unique(res["batch"], return_counts=True)
         size = dict(zip(ids.tolist(), counts.tolist()))
         wide = req["range_bits"] > thr
-        big = wide & (req["n"] >= 1 << 22)
+        big = wide & (req["n"] >= 1 << 23)
         # a launch never mixes narrow and wide requests; big wide ones run alone
         for b in np.unique(res["batch"]):
             members = res["batch"] == b
@@ -98,7 +98,7 @@ def test_plain_range_bits_threshold():
 
 def test_wide_requests_run_alone():
     req = _trace(count=60, rate=float("inf"), seed=5)
-    req["n"][::10] = 1 << 22
+    req["n"][::10] = 1 << 23
     req["range_bits"][::10] = 28
     res, _ = _run(req, budget=2 << 30)
     assert np.all(res["flags"] == 0)
