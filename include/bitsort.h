@@ -112,6 +112,28 @@ size_t bitsort_workspace_bytes(uint64_t n, uint32_t range_bits);
 int bitsort_u32_ws(const uint32_t *keys, uint64_t n, uint32_t range_bits, uint32_t *out,
                    void *workspace, size_t ws_bytes, bitsort_stream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sort of
+ * bitsort_u32, with the same arguments, result and errors, that allocates
+ * nothing.  Its workspace is one fixed device array of
+ * BITSORT_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs
+ * on until the process ends.
+ *   status  device pointer to one bitsort_status_t (8-byte aligned, not
+ *           overlapping keys or out) that receives this call's status when
+ *           the work has run; NULL to discard it.  n = 0 writes a zero status.
+ * Returns BITSORT_ERR_TOO_LARGE, before touching the device, when the
+ * problem's workspace would exceed the array: bitsort_workspace_bytes(n,
+ * range_bits) <= BITSORT_NOALLOC_SCRATCH_BYTES is the limit (10^6 keys over
+ * 2^24 need about 4.3 MB; 2^22 keys over 2^24 about 18.4 MB).  Every call on
+ * one GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (different streams, or different host threads) race and give undefined
+ * results.  The first call on a device looks up the array's address there.
+ */
+#define BITSORT_NOALLOC_SCRATCH_BYTES (32u << 20)
+int bitsort_u32_noalloc(const uint32_t *keys, uint64_t n, uint32_t range_bits, uint32_t *out,
+                        bitsort_status_t *status, bitsort_stream_t stream);
+
 /* Synchronise `stream`, then copy the status of the last call made on it
  * (library workspace) into *status. */
 int bitsort_get_status(bitsort_stream_t stream, bitsort_status_t *status);

@@ -56,6 +56,7 @@ _SIGS = {
     "bitsort_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
     "bitsort_workspace_bytes": (_c.c_size_t, [_u64, _u32]),
     "bitsort_u32_ws": (_c.c_int, [_vp, _u64, _u32, _vp, _vp, _c.c_size_t, _vp]),
+    "bitsort_u32_noalloc": (_c.c_int, [_vp, _u64, _u32, _vp, _vp, _vp]),
     "bitsort_radix_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
     "bitsort_radix_i32": (_c.c_int, [_vp, _u64, _vp, _vp]),
     "bitsort_radix_u64": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
@@ -152,6 +153,14 @@ def bitsort_workspace_bytes(n: int, range_bits: int) -> int:
 
 def bitsort_u32_ws(keys: int, n: int, range_bits: int, out: int, ws: int, ws_bytes: int, stream: int) -> int:
     return lib().bitsort_u32_ws(keys, n, range_bits, out, ws, ws_bytes, stream)
+
+
+def bitsort_u32_noalloc(keys: int, n: int, range_bits: int, out: int, status: int, stream: int) -> int:
+    """status: device address of one bitsort_status_t, or 0."""
+    return lib().bitsort_u32_noalloc(keys, n, range_bits, out, status, stream)
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 def bitsort_radix_u32(keys: int, n: int, key_bits: int, out: int, stream: int) -> int:

@@ -275,7 +275,7 @@ struct PendingTiming {
   hipEvent_t start, stop;
 };
 std::atomic<bool> g_prof_on{false};
-thread_local bool t_capturing = false;  // enqueueing into a graph capture: no timing events
+thread_local bool t_capturing = false;  // enqueueing into a graph capture or the no-allocation call: no timing events
 std::mutex g_prof_mu;
 std::vector<PendingTiming> g_prof_pending;
 uint64_t g_prof_launches[kKCount] = {};
@@ -345,12 +345,14 @@ uint32_t device_cus() {
   return static_cast<uint32_t>(c);
 }
 
+// status_to: where the call's status goes (the workspace header when null).
 int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, void* ws,
-              hipStream_t stream, int mode, uint32_t* dbg_bitmap, uint64_t* dbg_prefix) {
+              hipStream_t stream, int mode, uint32_t* dbg_bitmap, uint64_t* dbg_prefix,
+              Status* status_to = nullptr) {
   int rc = init_kernels();
   if (rc != BITSORT_OK) return rc;
   char* base = static_cast<char*>(ws);
-  Status* status = reinterpret_cast<Status*>(base);
+  Status* status = status_to != nullptr ? status_to : reinterpret_cast<Status*>(base);
   const uint64_t range = 1ull << p.rb;
   if (p.direct) {
     LaunchTimer timer(kKDirect, stream);
@@ -913,6 +915,36 @@ int radix_on_stream(const K* keys, const uint32_t* vals, uint64_t n, uint32_t ke
 
 #include "serve.inc"
 
+// ---- the no-allocation entry point --------------------------------------------
+// A fixed device array per GPU serves as the plain path's workspace for
+// bitsort_u32_noalloc; the loader places one copy on every GPU the library
+// runs on and it lives until the process ends.  In host code its name is a
+// host-side stand-in and never a device address: kernels and copies get the
+// address that hipGetSymbolAddress returns on the current device, looked up
+// once per device on its first call there.
+constexpr size_t kNoAllocBytes = BITSORT_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char noalloc_scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+int noalloc_scratch_of_device(void** ptr) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BITSORT_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)) != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return BITSORT_ERR_HIP;
+    }
+    g_noalloc_ptr[dev] = p;
+  }
+  *ptr = g_noalloc_ptr[dev];
+  return BITSORT_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -953,6 +985,38 @@ int bitsort_u32_ws(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32
     return hipMemsetAsync(workspace, 0, sizeof(Status), s) == hipSuccess ? BITSORT_OK : BITSORT_ERR_HIP;
   }
   return run_plain(p, keys, n, out, workspace, s, kEmit, nullptr, nullptr);
+}
+
+int bitsort_u32_noalloc(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32_t* out,
+                        bitsort_status_t* status, bitsort_stream_t stream) {
+  int rc = check_args(keys, n, range_bits, out);
+  if (rc != BITSORT_OK) return rc;
+  if (status != nullptr) {
+    if ((reinterpret_cast<uintptr_t>(status) & 7u) != 0) return BITSORT_ERR_INVALID_ARG;
+    auto meets = [&](const void* a) {  // [status, status + 16) against [a, a + 4n)
+      const uintptr_t s0 = reinterpret_cast<uintptr_t>(status), a0 = reinterpret_cast<uintptr_t>(a);
+      return s0 < a0 + 4 * n && a0 < s0 + sizeof(bitsort_status_t);
+    };
+    if (n > 0 && (meets(keys) || meets(out))) return BITSORT_ERR_INVALID_ARG;
+  }
+  Plan p;
+  make_plan(n, range_bits, &p);
+  if (p.bytes > kNoAllocBytes) return BITSORT_ERR_TOO_LARGE;  // decided before any device call
+  void* ws = nullptr;
+  if ((rc = noalloc_scratch_of_device(&ws)) != BITSORT_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n == 0) {
+    if (status != nullptr)  // a fill kernel, not a memset: the call may be stream-captured
+      hipLaunchKernelGGL(serve::k_fill_u64, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned long long*>(status),
+                         2u);
+    return launch_status();
+  }
+  static_assert(sizeof(Status) == sizeof(bitsort_status_t), "status layouts must match");
+  const bool was = t_capturing;
+  t_capturing = true;  // no timing events on this path
+  rc = run_plain(p, keys, n, out, ws, s, kEmit, nullptr, nullptr, reinterpret_cast<Status*>(status));
+  t_capturing = was;
+  return rc;
 }
 
 int bitsort_u32(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32_t* out, bitsort_stream_t stream) {

@@ -129,3 +129,16 @@ def test_tuning_cache_plumbing(lib, tmp_path):
     _lib.bitsort_tuning_clear()
     rc, sb3, tl3, nb3, ep3 = _lib.bitsort_plan_info(1 << 25, 27)
     assert (sb3, tl3) != (17, 13)
+
+
+def test_noalloc_rejects_beyond_its_array(lib):
+    """The no-allocation entry point refuses, before touching the device, a
+    problem whose workspace exceeds its fixed device array."""
+    E = _lib
+    fake = 1 << 20  # never dereferenced
+    n = 1 << 24
+    assert E.bitsort_workspace_bytes(n, 28) > E.NOALLOC_SCRATCH_BYTES
+    assert E.bitsort_u32_noalloc(fake, n, 28, fake + (1 << 30), 0, 0) == E.BITSORT_ERR_TOO_LARGE
+    assert E.bitsort_u32_noalloc(fake, 10, 33, fake + 4096, 0, 0) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_u32_noalloc(fake, 100, 10, fake + 4096, fake + 4, 0) == E.BITSORT_ERR_INVALID_ARG  # status in keys
+    assert E.bitsort_u32_noalloc(fake, 100, 10, fake + 4096, fake + 8192 + 3, 0) == E.BITSORT_ERR_INVALID_ARG
