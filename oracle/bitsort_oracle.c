@@ -266,157 +266,172 @@ int oracle_bitmap_sort_segments_u32(const uint32_t *keys, const uint64_t *offset
 
 /* ---- the paper's Algorithm 1 ---------------------------------------------- */
 
-/* BitwiseSort1 on unsigned 32-bit keys: for k = 0 .. passes-1, a stable
- * partition of A by bit k (elements with bit k = 0 first, each group in its
- * previous order).  passes = 32 sorts every uint32 array (reading O5); fewer
- * passes leave A sorted by its low `passes` bits (Theorem 1). */
+/* One pass of Algorithm 1 (S5), written from its definition rather than from
+ * the printed listing: a stable partition of src[0..n) by one bit into dst.
+ * Elements whose bit `bit` equals `front` go first and the others after them,
+ * each group in the order it had in src.  The size of the first group is
+ * counted beforehand, so both groups are placed in a single sweep; it is
+ * returned. */
+static uint64_t split_by_bit_u32(const uint32_t *src, uint32_t *dst, uint64_t n, uint32_t bit, uint32_t front)
+{
+    uint64_t first = 0;
+    for (uint64_t i = 0; i < n; i++)
+        first += (oracle_bit_value(src[i], bit) == front);
+    uint64_t at_front = 0, at_back = first;
+    for (uint64_t i = 0; i < n; i++) {
+        if (oracle_bit_value(src[i], bit) == front)
+            dst[at_front++] = src[i];
+        else
+            dst[at_back++] = src[i];
+    }
+    return first;
+}
+
+/* BitwiseSort1 on unsigned 32-bit keys: for k = 0 .. passes-1, the stable
+ * partition by bit k with the zeros first.  The passes alternate between A and
+ * one scratch array.  passes = 32 sorts every uint32 array (reading O5);
+ * fewer passes leave A ordered by its low `passes` bits (Theorem 1). */
 int oracle_bitwise_sort1_u32(uint32_t *A, uint64_t n, uint32_t passes)
 {
     if (passes > 32 || (n > 0 && A == NULL))
         return ORACLE_ERR_ARG;
     if (n == 0)
         return ORACLE_OK;
-    uint32_t *A0 = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
-    uint32_t *A1 = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
-    if (A0 == NULL || A1 == NULL) {
-        free(A0);
-        free(A1);
+    uint32_t *scratch = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    if (scratch == NULL)
         return ORACLE_ERR_NOMEM;
-    }
+    uint32_t *from = A, *to = scratch;
     for (uint32_t k = 0; k < passes; k++) {
-        uint64_t n0 = 0, n1 = 0;
-        for (uint64_t i = 0; i < n; i++) {
-            if (A[i] & (1u << k))
-                A1[n1++] = A[i];
-            else
-                A0[n0++] = A[i];
-        }
-        for (uint64_t i = 0; i < n0; i++)
-            A[i] = A0[i];
-        for (uint64_t i = 0; i < n1; i++)
-            A[n0 + i] = A1[i];
+        split_by_bit_u32(from, to, n, k, 0u);
+        uint32_t *t = from;
+        from = to;
+        to = t;
     }
-    free(A0);
-    free(A1);
+    if (from != A)
+        memcpy(A, from, (size_t)n * sizeof(uint32_t));
+    free(scratch);
     return ORACLE_OK;
 }
 
-/* BitwiseSort1 for T = uint64 (t = 64 bits): the same stable partition by
- * bit k, for k = 0 .. passes-1, passes <= 64. */
+/* The same pass for T = uint64: bit k of a 64-bit element, k < 64. */
+static void split_by_bit_u64(const uint64_t *src, uint64_t *dst, uint64_t n, uint32_t k)
+{
+    const uint64_t mask = (uint64_t)1 << k;
+    uint64_t zeros = 0;
+    for (uint64_t i = 0; i < n; i++)
+        zeros += ((src[i] & mask) == 0);
+    uint64_t z = 0, o = zeros;
+    for (uint64_t i = 0; i < n; i++) {
+        if ((src[i] & mask) == 0)
+            dst[z++] = src[i];
+        else
+            dst[o++] = src[i];
+    }
+}
+
+/* BitwiseSort1 for T = uint64 (t = 64 bits): the stable partition by bit k,
+ * zeros first, for k = 0 .. passes-1, passes <= 64. */
 int oracle_bitwise_sort1_u64(uint64_t *A, uint64_t n, uint32_t passes)
 {
     if (passes > 64 || (n > 0 && A == NULL))
         return ORACLE_ERR_ARG;
     if (n == 0)
         return ORACLE_OK;
-    uint64_t *A0 = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
-    uint64_t *A1 = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
-    if (A0 == NULL || A1 == NULL) {
-        free(A0);
-        free(A1);
+    uint64_t *scratch = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    if (scratch == NULL)
         return ORACLE_ERR_NOMEM;
-    }
+    uint64_t *from = A, *to = scratch;
     for (uint32_t k = 0; k < passes; k++) {
-        const uint64_t bit = (uint64_t)1 << k;
-        uint64_t n0 = 0, n1 = 0;
-        for (uint64_t i = 0; i < n; i++) {
-            if (A[i] & bit)
-                A1[n1++] = A[i];
-            else
-                A0[n0++] = A[i];
-        }
-        for (uint64_t i = 0; i < n0; i++)
-            A[i] = A0[i];
-        for (uint64_t i = 0; i < n1; i++)
-            A[n0 + i] = A1[i];
+        split_by_bit_u64(from, to, n, k);
+        uint64_t *t = from;
+        from = to;
+        to = t;
     }
-    free(A0);
-    free(A1);
+    if (from != A)
+        memcpy(A, from, (size_t)n * sizeof(uint64_t));
+    free(scratch);
     return ORACLE_OK;
 }
 
-/* BitwiseSort1 on records (K[i], V[i]): the bit test reads the key, and the
- * partition moves the whole record, so each value travels with its key and
- * records with equal keys keep their input order. */
+/* The pass on records (key, value): the bit test reads the key and the whole
+ * record moves, so each value stays with its key. */
+static void split_records_by_bit(const uint32_t *sk, const uint32_t *sv, uint32_t *dk, uint32_t *dv, uint64_t n,
+                                 uint32_t k)
+{
+    uint64_t zeros = 0;
+    for (uint64_t i = 0; i < n; i++)
+        zeros += (oracle_bit_value(sk[i], k) == 0u);
+    uint64_t lo = 0, hi = zeros;
+    for (uint64_t i = 0; i < n; i++) {
+        uint64_t *slot = (oracle_bit_value(sk[i], k) == 0u) ? &lo : &hi;
+        dk[*slot] = sk[i];
+        dv[*slot] = sv[i];
+        (*slot)++;
+    }
+}
+
+/* BitwiseSort1 on records (K[i], V[i]): records with equal keys keep their
+ * input order, since every pass is stable. */
 int oracle_bitwise_sort1_pairs_u32(uint32_t *K, uint32_t *V, uint64_t n, uint32_t passes)
 {
     if (passes > 32 || (n > 0 && (K == NULL || V == NULL)))
         return ORACLE_ERR_ARG;
     if (n == 0)
         return ORACLE_OK;
-    uint32_t *K0 = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
-    uint32_t *K1 = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
-    uint32_t *V0 = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
-    uint32_t *V1 = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
-    if (K0 == NULL || K1 == NULL || V0 == NULL || V1 == NULL) {
-        free(K0);
-        free(K1);
-        free(V0);
-        free(V1);
+    uint32_t *sk = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    uint32_t *sv = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    if (sk == NULL || sv == NULL) {
+        free(sk);
+        free(sv);
         return ORACLE_ERR_NOMEM;
     }
+    uint32_t *fk = K, *fv = V, *tk = sk, *tv = sv;
     for (uint32_t k = 0; k < passes; k++) {
-        uint64_t n0 = 0, n1 = 0;
-        for (uint64_t i = 0; i < n; i++) {
-            if (K[i] & (1u << k)) {
-                K1[n1] = K[i];
-                V1[n1++] = V[i];
-            } else {
-                K0[n0] = K[i];
-                V0[n0++] = V[i];
-            }
-        }
-        for (uint64_t i = 0; i < n0; i++) {
-            K[i] = K0[i];
-            V[i] = V0[i];
-        }
-        for (uint64_t i = 0; i < n1; i++) {
-            K[n0 + i] = K1[i];
-            V[n0 + i] = V1[i];
-        }
+        split_records_by_bit(fk, fv, tk, tv, n, k);
+        uint32_t *t = fk;
+        fk = tk;
+        tk = t;
+        t = fv;
+        fv = tv;
+        tv = t;
     }
-    free(K0);
-    free(K1);
-    free(V0);
-    free(V1);
+    if (fk != K) {
+        memcpy(K, fk, (size_t)n * sizeof(uint32_t));
+        memcpy(V, fv, (size_t)n * sizeof(uint32_t));
+    }
+    free(sk);
+    free(sv);
     return ORACLE_OK;
 }
 
-/* BitwiseSort on signed 32-bit keys: negatives and non-negatives are split
- * apart, each part is sorted by BitwiseSort1 over the t-1 = 31 bits below the
- * sign bit (all its elements share the sign bit), and the negatives are put
- * first. */
+/* BitwiseSort on signed 32-bit keys (S5): first the sign split -- the
+ * negatives, whose sign bit is 1, in front of the rest, each group in input
+ * order -- then each group sorted by BitwiseSort1 over the t-1 = 31 bits below
+ * the sign bit, which every element of a group shares. */
 int oracle_bitwise_sort_i32(int32_t *A, uint64_t n)
 {
     if (n > 0 && A == NULL)
         return ORACLE_ERR_ARG;
     if (n == 0)
         return ORACLE_OK;
-    uint32_t *minus = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
-    uint32_t *plus = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
-    if (minus == NULL || plus == NULL) {
-        free(minus);
-        free(plus);
+    uint32_t *bits = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    uint32_t *grouped = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    if (bits == NULL || grouped == NULL) {
+        free(bits);
+        free(grouped);
         return ORACLE_ERR_NOMEM;
     }
-    uint64_t nm = 0, np = 0;
-    for (uint64_t i = 0; i < n; i++) {
-        if (A[i] < 0)
-            minus[nm++] = (uint32_t)A[i];
-        else
-            plus[np++] = (uint32_t)A[i];
-    }
-    int rc = oracle_bitwise_sort1_u32(minus, nm, 31);
+    for (uint64_t i = 0; i < n; i++)
+        bits[i] = (uint32_t)A[i];
+    const uint64_t negatives = split_by_bit_u32(bits, grouped, n, 31u, 1u);
+    int rc = oracle_bitwise_sort1_u32(grouped, negatives, 31);
     if (rc == ORACLE_OK)
-        rc = oracle_bitwise_sort1_u32(plus, np, 31);
-    if (rc == ORACLE_OK) {
-        for (uint64_t i = 0; i < nm; i++)
-            A[i] = (int32_t)minus[i];
-        for (uint64_t i = 0; i < np; i++)
-            A[nm + i] = (int32_t)plus[i];
-    }
-    free(minus);
-    free(plus);
+        rc = oracle_bitwise_sort1_u32(grouped + negatives, n - negatives, 31);
+    if (rc == ORACLE_OK)
+        for (uint64_t i = 0; i < n; i++)
+            A[i] = (int32_t)grouped[i];
+    free(bits);
+    free(grouped);
     return rc;
 }
 

@@ -28,12 +28,11 @@ MUTANTS = {
     "bit_value_index": ("return ((x & (1u << i)) == 0) ? 0u : 1u;",
                         "return ((x & (1u << (i ^ 1u))) == 0) ? 0u : 1u;"),
     "bitmap_words_extra": ("return r < 32 ? 1 : r / 32;", "return r < 32 ? 1 : r / 32 + 1;"),
-    "radix_ones_first": ("            if (A[i] & (1u << k))\n                A1[n1++] = A[i];",
-                         "            if (!(A[i] & (1u << k)))\n                A1[n1++] = A[i];"),
-    "radix_unstable": ("            A[n0 + i] = A1[i];\n    }\n    free(A0);\n    free(A1);\n    return ORACLE_OK;\n}\n\n/* BitwiseSort1 for T",
-                       "            A[n0 + i] = A1[n1 - 1 - i];\n    }\n    free(A0);\n    free(A1);\n    return ORACLE_OK;\n}\n\n/* BitwiseSort1 for T"),
-    "sign_split_zero": ("        if (A[i] < 0)\n            minus[nm++]", "        if (A[i] <= 0)\n            minus[nm++]"),
-    "signed_lost_pass": ("rc = oracle_bitwise_sort1_u32(plus, np, 31);", "rc = oracle_bitwise_sort1_u32(plus, np, 30);"),
+    "radix_ones_first": ("        split_by_bit_u32(from, to, n, k, 0u);", "        split_by_bit_u32(from, to, n, k, 1u);"),
+    "radix_unstable": ("            dst[at_back++] = src[i];", "            dst[n - 1 - (at_back++ - first)] = src[i];"),
+    "sign_split_order": ("split_by_bit_u32(bits, grouped, n, 31u, 1u);", "split_by_bit_u32(bits, grouped, n, 31u, 0u);"),
+    "signed_lost_pass": ("rc = oracle_bitwise_sort1_u32(grouped + negatives, n - negatives, 31);",
+                         "rc = oracle_bitwise_sort1_u32(grouped + negatives, n - negatives, 30);"),
     "scan_dropped_term": ("prefix[w + 1] = prefix[w] + oracle_count_ones(bitmap[w]);",
                           "prefix[w + 1] = oracle_count_ones(bitmap[w]);"),
     "counting_collapses": ("        count[keys[i]]++;", "        count[keys[i]] = 1;"),
@@ -45,9 +44,8 @@ MUTANTS = {
     "w64_variant_mask": ("bitmap[k >> 6] = bitmap[k >> 6] | ((uint64_t)1 << (k & 63));",
                          "bitmap[k >> 6] = bitmap[k >> 6] | ((uint64_t)1 << (k & 31));"),
     "bin_repl_reversed": ("out[15 - d] = oracle_bit_value", "out[d] = oracle_bit_value"),
-    "u64_radix_32bit_shift": ("const uint64_t bit = (uint64_t)1 << k;", "const uint64_t bit = (uint64_t)(1u << (k & 31));"),
-    "pairs_value_left_behind": ("                K1[n1] = K[i];\n                V1[n1++] = V[i];",
-                                "                K1[n1] = K[i];\n                V1[n1++] = V[n - 1 - i];"),
+    "u64_radix_32bit_shift": ("const uint64_t mask = (uint64_t)1 << k;", "const uint64_t mask = (uint64_t)(1u << (k & 31));"),
+    "pairs_value_left_behind": ("        dv[*slot] = sv[i];", "        dv[*slot] = sv[n - 1 - i];"),
 }
 
 _RUNNER = """
