@@ -447,6 +447,9 @@ typedef struct bitsort_serve_config {
     uint32_t _pad;
     double sim_overhead_s;
     double sim_keys_per_s;
+    uint32_t *const *outputs;    /* NULL, or a host array of `count` device pointers: request i's sorted keys
+                                    (results[i].count of them) are copied to outputs[i] (NULL: not copied)
+                                    on its launch's stream before the launch counts as done */
 } bitsort_serve_config_t;
 
 typedef struct bitsort_serve_stats {

@@ -233,7 +233,7 @@ void set_lds_attr(K kernel, uint32_t bytes) {
 
 int init_kernels() {
   std::call_once(g_attr_once, [] {
-    set_lds_attr(k_partition<256, 16>, kLdsBytes);
+    set_lds_attr(k_partition<1024, 4>, kLdsBytes);
     set_lds_attr(k_partition<512, 16>, kLdsBytes);
     set_lds_attr(k_partition<1024, 16>, kLdsBytes);
     set_lds_attr(k_partition<1024, 32>, kLdsBytes);
@@ -312,9 +312,9 @@ int launch_partition(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* 
   const size_t part_lds = 4ull * (32 + round_up4(p.nb) + p.tile_keys);
   LaunchTimer timer(kKPartition, stream);
   switch (p.tile_log2) {
-    case 12:
-      hipLaunchKernelGGL((k_partition<256, 16>), dim3(p.nt), dim3(256), part_lds, stream, keys, n, range, p.sb, p.nb,
-                         staging, table, vec_ok, p.bias);
+    case 12:  // 4096-key tiles: 1024 threads of 4 keys, so that a small input's few tiles still fill the CUs
+      hipLaunchKernelGGL((k_partition<1024, 4>), dim3(p.nt), dim3(1024), part_lds, stream, keys, n, range, p.sb,
+                         p.nb, staging, table, vec_ok, p.bias);
       break;
     case 13:
       hipLaunchKernelGGL((k_partition<512, 16>), dim3(p.nt), dim3(512), part_lds, stream, keys, n, range, p.sb, p.nb,
@@ -346,9 +346,12 @@ uint32_t device_cus() {
 }
 
 // status_to: where the call's status goes (the workspace header when null).
+// defer_finish: the caller reads the status through the library
+// (read_plain_status), so the two-kernel path leaves its finish step pending
+// in the workspace header instead of launching it.
 int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, void* ws,
               hipStream_t stream, int mode, uint32_t* dbg_bitmap, uint64_t* dbg_prefix,
-              Status* status_to = nullptr) {
+              Status* status_to = nullptr, bool defer_finish = false) {
   int rc = init_kernels();
   if (rc != BITSORT_OK) return rc;
   char* base = static_cast<char*>(ws);
@@ -368,6 +371,8 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
   uint32_t* bitvec = reinterpret_cast<uint32_t*>(base + p.off_bitvec);
   uint64_t* chunk_base = reinterpret_cast<uint64_t*>(base + p.off_chunk);
   if (p.via_bitvec && mode == kDumpBitmap) bitvec = dbg_bitmap;  // the mark step's bit-vector is the dump
+  const bool defer = defer_finish && mode == kEmit && status_to == nullptr;
+  Status* pending = defer ? status : nullptr;
   {
     LaunchTimer timer(kKSlice, stream);
     const uint32_t cus = device_cus();
@@ -377,7 +382,7 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
       const uint32_t grid = std::max(8u, cus & ~7u);
       auto kernel = p.short_units ? k_slice_seq<kSliceBlock, kSliceUnroll, 16> : k_slice_seq<kSliceBlock, kSliceUnroll, 64>;
       hipLaunchKernelGGL(kernel, dim3(grid), dim3(kSliceBlock), p.slice_lds, stream, staging, table, p.nt,
-                         p.tile_keys, p.sb, p.nb, out, info, 0u - p.bias);
+                         p.tile_keys, p.sb, p.nb, out, info, 0u - p.bias, n, pending);
       rc = launch_status();
     } else {
     const uint32_t grid = 8u * ((p.nb + 7u) / 8u);
@@ -388,7 +393,7 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(kSliceBlock), p.slice_lds, stream, staging, table, p.nt,
                        p.tile_keys, p.sb, p.nb, p.stage_cap, out, info,
                        p.via_bitvec ? static_cast<int>(kToBitVector) : mode, dbg_bitmap, dbg_prefix, bitvec,
-                       chunk_base, 0u - p.bias);
+                       chunk_base, 0u - p.bias, n, pending);
     rc = launch_status();
     }
   }
@@ -400,6 +405,7 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
     rc = launch_status();
     if (rc != BITSORT_OK || mode != kEmit) return rc;
   }
+  if (defer) return BITSORT_OK;
   LaunchTimer timer(kKFinish, stream);
   hipLaunchKernelGGL((k_finish<kSliceBlock>), dim3(1), dim3(kSliceBlock), 0, stream, n, p.nb, info, status, out);
   return launch_status();
@@ -486,10 +492,19 @@ int check_multi_args(const uint32_t* const* keys, const uint64_t* n, const uint8
 // HBM bit-vector, as on the single-array path; such an array takes a split of
 // 4 or more (measured best) and slices of at least one emission chunk (2^15
 // bits).
-void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8_t* range_bits,
-                     uint32_t* const* out, uint32_t count, MultiPlan* p) {
+// Launch limits of the multi kernels: a grid holds at most 2^32 work-items
+// (HSA dispatch sizes are 32-bit), so tiles and slices stay below 2^22
+// workgroups of up to 1024 threads and chunks below 2^24 of 256; the
+// descriptors' first-tile, first-slice and first-chunk fields are 32-bit.
+constexpr uint64_t kMultiMaxTiles = (1ull << 22) - 8;
+constexpr uint64_t kMultiMaxSlices = (1ull << 22) - 8;
+constexpr uint64_t kMultiMaxChunks = (1ull << 24) - 1;
+
+// Returns BITSORT_ERR_TOO_LARGE, before any field of *p is used, when the
+// arrays together pass a launch limit; the sums are taken in 64 bits.
+int make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8_t* range_bits,
+                    uint32_t* const* out, uint32_t count, MultiPlan* p) {
   *p = MultiPlan();
-  p->desc.resize(count);
   auto via_bitvec = [&](uint32_t a) {
     const uint32_t rb = range_bits[a];
     return rb >= 21 && (1ull << rb) / 8u <= 2 * n[a];
@@ -518,6 +533,17 @@ void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8
   }
   p->tile_log2 = weighted >= 64 * total && total > 0 ? 14u : 12u;
   const uint64_t tile_keys = 1ull << p->tile_log2;
+  {
+    uint64_t tiles = 0, slices = 0, chunks = 0;
+    for (uint32_t a = 0; a < count; ++a) {
+      const uint32_t rb = range_bits[a], sb = slice_bits(a, split);
+      tiles += (n[a] + tile_keys - 1) / tile_keys;
+      slices += rb > sb ? 1ull << (rb - sb) : 1ull;
+      if (via_bitvec(a)) chunks += 1ull << (rb - kChunkLog2Bits);
+    }
+    if (tiles > kMultiMaxTiles || slices > kMultiMaxSlices || chunks > kMultiMaxChunks) return BITSORT_ERR_TOO_LARGE;
+  }
+  p->desc.resize(count);
   for (uint32_t a = 0; a < count; ++a) {
     MultiDesc& d = p->desc[a];
     const uint32_t rb = range_bits[a];
@@ -561,6 +587,7 @@ void make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8
   p->off_chunk = o;
   o = align256(o + 8ull * p->chunks);
   p->bytes = o;
+  return BITSORT_OK;
 }
 
 // Enqueue the three multi kernels; the descriptors must already be on the
@@ -862,10 +889,24 @@ int grow(void** ptr, size_t* have, size_t need, hipStream_t stream) {
   return BITSORT_OK;
 }
 
-int copy_status(const void* dev_status, hipStream_t stream, bitsort_status_t* st) {
+// Status of the last sort on a workspace (synchronises `stream`).  A plain
+// sort that left its finish step pending gets it now: k_finish runs on the
+// stream (totals, flags, compaction after a repeated key) and clears the
+// pending mark, so a second read finds the final status.
+int read_plain_status(void* ws, hipStream_t stream, bitsort_status_t* st) {
   if (hipStreamSynchronize(stream) != hipSuccess) return BITSORT_ERR_HIP;
   Status s{};
-  if (hipMemcpy(&s, dev_status, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess) return BITSORT_ERR_HIP;
+  if (hipMemcpy(&s, ws, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess) return BITSORT_ERR_HIP;
+  if (s.done == kFinishPending) {
+    PendingFinish d{};
+    if (hipMemcpy(&d, static_cast<char*>(ws) + kPendingOffset, sizeof(d), hipMemcpyDeviceToHost) != hipSuccess)
+      return BITSORT_ERR_HIP;
+    if (d.nb == 0 || d.info == nullptr) return BITSORT_ERR_INVALID_ARG;
+    hipLaunchKernelGGL((k_finish<kSliceBlock>), dim3(1), dim3(kSliceBlock), 0, stream, d.n, d.nb, d.info,
+                       static_cast<Status*>(ws), d.out);
+    if (launch_status() != BITSORT_OK || hipStreamSynchronize(stream) != hipSuccess) return BITSORT_ERR_HIP;
+    if (hipMemcpy(&s, ws, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess) return BITSORT_ERR_HIP;
+  }
   st->flags = s.flags;
   st->_pad = 0;
   st->count = s.count;
@@ -981,10 +1022,11 @@ int bitsort_u32_ws(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32
   make_plan(n, range_bits, &p);
   if (ws_bytes < p.bytes) return BITSORT_ERR_NO_MEMORY;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (n == 0) {
-    return hipMemsetAsync(workspace, 0, sizeof(Status), s) == hipSuccess ? BITSORT_OK : BITSORT_ERR_HIP;
+  if (n == 0) {  // a zero status; a fill kernel, not a memset: the call may be stream-captured
+    hipLaunchKernelGGL(serve::k_fill_u64, dim3(1), dim3(64), 0, s, static_cast<unsigned long long*>(workspace), 2u);
+    return launch_status();
   }
-  return run_plain(p, keys, n, out, workspace, s, kEmit, nullptr, nullptr);
+  return run_plain(p, keys, n, out, workspace, s, kEmit, nullptr, nullptr, nullptr, true);
 }
 
 int bitsort_u32_noalloc(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32_t* out,
@@ -1035,7 +1077,7 @@ int bitsort_u32(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32_t*
   rc = grow(&c.ws, &c.bytes, p.bytes, s);
   if (rc != BITSORT_OK) return rc;
   c.last_empty = false;
-  return run_plain(p, keys, n, out, c.ws, s, kEmit, nullptr, nullptr);
+  return run_plain(p, keys, n, out, c.ws, s, kEmit, nullptr, nullptr, nullptr, true);
 }
 
 size_t bitsort_radix_workspace_bytes(uint64_t n, uint32_t key_bits) {
@@ -1054,7 +1096,10 @@ int bitsort_radix_u32_ws(const uint32_t* keys, uint64_t n, uint32_t key_bits, ui
   make_radix_plan(n, key_bits, 4, false, &p);
   if (ws_bytes < p.bytes) return BITSORT_ERR_NO_MEMORY;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (n == 0) return hipMemsetAsync(workspace, 0, sizeof(Status), s) == hipSuccess ? BITSORT_OK : BITSORT_ERR_HIP;
+  if (n == 0) {  // a zero status through a fill kernel (the call may be stream-captured)
+    hipLaunchKernelGGL(serve::k_fill_u64, dim3(1), dim3(64), 0, s, static_cast<unsigned long long*>(workspace), 2u);
+    return launch_status();
+  }
   if ((rc = init_kernels()) != BITSORT_OK) return rc;
   return run_radix<uint32_t, false>(p, keys, nullptr, n, key_bits, 0u, out, nullptr, workspace, s);
 }
@@ -1121,7 +1166,7 @@ int bitsort_i32(const int32_t* keys_s, uint64_t n, uint32_t range_bits, int32_t*
   rc = grow(&c.ws, &c.bytes, p.bytes, s);
   if (rc != BITSORT_OK) return rc;
   c.last_empty = false;
-  return run_plain(p, keys, n, out, c.ws, s, kEmit, nullptr, nullptr);
+  return run_plain(p, keys, n, out, c.ws, s, kEmit, nullptr, nullptr, nullptr, true);
 }
 
 int bitsort_get_status(bitsort_stream_t stream, bitsort_status_t* status) {
@@ -1139,12 +1184,12 @@ int bitsort_get_status(bitsort_stream_t stream, bitsort_status_t* status) {
     }
     ws = c.ws;
   }
-  return copy_status(ws, s, status);
+  return read_plain_status(ws, s, status);
 }
 
 int bitsort_workspace_status(const void* workspace, bitsort_stream_t stream, bitsort_status_t* status) {
   if (workspace == nullptr || status == nullptr) return BITSORT_ERR_INVALID_ARG;
-  return copy_status(workspace, static_cast<hipStream_t>(stream), status);
+  return read_plain_status(const_cast<void*>(workspace), static_cast<hipStream_t>(stream), status);
 }
 
 int bitsort_generate_u32(uint32_t* out, uint64_t first, uint64_t count, uint32_t range_bits, uint64_t seed,
@@ -1209,7 +1254,7 @@ int bitsort_batch_ptr_u32(const uint32_t* const* keys, const uint64_t* n, const 
   int rc = check_multi_args(keys, n, range_bits, out, count);
   if (rc != BITSORT_OK) return rc;
   MultiPlan p;
-  make_multi_plan(keys, n, range_bits, out, count, &p);
+  if ((rc = make_multi_plan(keys, n, range_bits, out, count, &p)) != BITSORT_OK) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lock(g_mu);
   StreamCtx& c = ctx_for(stream);
@@ -1313,7 +1358,9 @@ int bitsort_graph_create_u32(const uint32_t* keys, uint64_t n, uint32_t range_bi
     delete g;
     return BITSORT_ERR_NO_MEMORY;
   }
-  rc = capture(g, [&](hipStream_t cs) { return run_plain(p, keys, n, out, g->ws, cs, kEmit, nullptr, nullptr); });
+  rc = capture(g, [&](hipStream_t cs) {
+    return run_plain(p, keys, n, out, g->ws, cs, kEmit, nullptr, nullptr, nullptr, true);
+  });
   if (rc != BITSORT_OK) {
     bitsort_graph_destroy(g);
     return rc;
@@ -1362,11 +1409,11 @@ int bitsort_graph_status(bitsort_graph_t* graph, bitsort_stream_t stream, bitsor
   if (count > (graph->batch ? graph->segments : 1u)) return BITSORT_ERR_INVALID_ARG;
   if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return BITSORT_ERR_HIP;
   if (count == 0) return BITSORT_OK;
-  const char* src = static_cast<const char*>(graph->ws) + (graph->batch ? kHeaderBytes : 0);
+  if (!graph->batch) return read_plain_status(graph->ws, static_cast<hipStream_t>(stream), status);
+  const char* src = static_cast<const char*>(graph->ws) + kHeaderBytes;
   static_assert(sizeof(Status) == sizeof(bitsort_status_t), "status layouts must match");
   if (hipMemcpy(status, src, sizeof(bitsort_status_t) * count, hipMemcpyDeviceToHost) != hipSuccess)
     return BITSORT_ERR_HIP;
-  if (!graph->batch) status[0]._pad = 0;
   return BITSORT_OK;
 }
 
@@ -1439,7 +1486,7 @@ int bitsort_autotune_u32(uint64_t n, uint32_t range_bits, int reps, bitsort_stre
           continue;
         rc = grow(&ws, &ws_bytes, p.bytes, s);
         if (rc != BITSORT_OK) break;
-        const float ms = time_ms([&] { return run_plain(p, keys, n, out, ws, s, kEmit, nullptr, nullptr); },
+        const float ms = time_ms([&] { return run_plain(p, keys, n, out, ws, s, kEmit, nullptr, nullptr, nullptr, true); },
                                  reps, s, &rc);
         if (rc == BITSORT_OK && ms >= 0.f && ms < best_ms) {
           best_ms = ms;
@@ -1584,7 +1631,7 @@ int bitsort_serve_run(const bitsort_request_t* requests, uint32_t count, const b
   }
   {
     serve::HipExecutor ex;  // its destructor waits for every slot stream
-    rc = ex.init(static_cast<char*>(base), c.streams, c.verify != 0, c.max_batch_requests);
+    rc = ex.init(static_cast<char*>(base), c.streams, c.verify != 0, c.max_batch_requests, c.outputs);
     if (rc == BITSORT_OK) rc = serve::schedule(ex, arena, requests, count, c, results, stats, false);
   }
   if (c.arena == nullptr) {

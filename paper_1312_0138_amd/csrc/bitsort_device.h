@@ -17,8 +17,24 @@ constexpr uint32_t kWave = 64;
 // bitsort_status_t followed by private counters).
 struct Status {
   uint32_t flags;   // BITSORT_STATUS_* bits
-  uint32_t done;    // blocks finished (last-block detection)
+  uint32_t done;    // kFinishPending while the totals wait for the status read, else 0
   uint64_t count;   // keys written
+};
+
+// A two-kernel plain sort whose caller reads its status through the library
+// does not launch its one-workgroup finish step: the slice kernel leaves
+// Status::done = kFinishPending and, kPendingOffset bytes into the workspace,
+// what the finish step needs.  Reading the status then runs that step (totals,
+// flags and, only after a repeated key, the compaction of the output) on the
+// stream before copying the status out.
+constexpr uint32_t kFinishPending = 0x464E5350u;
+constexpr uint32_t kPendingOffset = 64;
+struct PendingFinish {
+  uint64_t n;             // keys given
+  const uint64_t* info;   // per-slice (base, ones, keys) triples
+  uint32_t* out;          // the sorted output
+  uint32_t nb;            // slices
+  uint32_t _pad;
 };
 
 __device__ __forceinline__ uint32_t lane_id() {
@@ -58,21 +74,43 @@ __device__ __forceinline__ uint32_t wave_prefix_small(uint32_t c, uint32_t* tota
   return p;
 }
 
-// Inclusive wave scan of arbitrary u32 values (Kogge-Stone over lanes).
+// DPP lane moves of a wave64 (four rows of 16 lanes): row_shr:k takes lane
+// i - k of the same row (0 past the row's start, bound_ctrl), row_bcast:15
+// and row_bcast:31 take lane 15 of the previous row and lane 31 into the
+// rows the row mask enables (0 in the others).
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ uint32_t dpp_or_zero(uint32_t v) {
+  return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, ROW_MASK, 0xf, BOUND));
+}
+
+// Inclusive scan of u32 values over the 64 lanes (every lane active): sums
+// within each row of 16 by shifts of 1, 2, 4 and 8 lanes, then row 0's total
+// into row 1 and row 2's into row 3 (row_bcast:15), then the first two rows'
+// total into rows 2 and 3 (row_bcast:31).  Six VALU moves instead of six
+// LDS-routed shuffles.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-  const uint32_t lane = lane_id();
-#pragma unroll
-  for (uint32_t d = 1; d < kWave; d <<= 1) {
-    const uint32_t y = __shfl_up(v, d, kWave);
-    if (lane >= d) v += y;
-  }
+  v += dpp_or_zero<0x111, 0xf, true>(v);  // row_shr:1
+  v += dpp_or_zero<0x112, 0xf, true>(v);  // row_shr:2
+  v += dpp_or_zero<0x114, 0xf, true>(v);  // row_shr:4
+  v += dpp_or_zero<0x118, 0xf, true>(v);  // row_shr:8
+  v += dpp_or_zero<0x142, 0xa, false>(v); // row_bcast:15
+  v += dpp_or_zero<0x143, 0xc, false>(v); // row_bcast:31
   return v;
 }
 
+// Sum of u32 values over the wave (mod 2^32), in a scalar register.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+  return __builtin_amdgcn_readlane(wave_incl_scan(v), kWave - 1);
+}
+
+// Sum of u64 values over the wave (mod 2^64): the low 32 bits in two 16-bit
+// halves (each sum stays below 2^22) and the high 32 bits, each summed over
+// the lanes in 32 bits.
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-  for (uint32_t d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-  return v;
+  const uint64_t a = wave_sum_u32(static_cast<uint32_t>(v) & 0xFFFFu);
+  const uint64_t b = wave_sum_u32(static_cast<uint32_t>(v) >> 16);
+  const uint64_t c = wave_sum_u32(static_cast<uint32_t>(v >> 32));
+  return a + (b << 16) + (c << 32);
 }
 
 // Exclusive block scan of one u32 per thread.  `scratch` holds BLOCK/64

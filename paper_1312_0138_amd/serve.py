@@ -19,10 +19,10 @@ RESULT = np.dtype([("launch_s", "<f8"), ("ready_s", "<f8"), ("done_s", "<f8"), (
 CONFIG = np.dtype([("arena", "<u8"), ("budget_bytes", "<u8"), ("streams", "<u4"), ("max_batch_requests", "<u4"),
                    ("max_batch_keys", "<u8"), ("plain_range_bits", "<u4"), ("verify", "<u4"), ("simulate", "<u4"),
                    ("pad", "<u4"),
-                   ("sim_overhead_s", "<f8"), ("sim_keys_per_s", "<f8")])
+                   ("sim_overhead_s", "<f8"), ("sim_keys_per_s", "<f8"), ("outputs", "<u8")])
 STATS = np.dtype([("makespan_s", "<f8"), ("keys", "<u8"), ("launches", "<u4"),
                   ("max_inflight_requests", "<u4"), ("peak_bytes", "<u8")])
-assert REQUEST.itemsize == 32 and RESULT.itemsize == 48 and CONFIG.itemsize == 64 and STATS.itemsize == 32
+assert REQUEST.itemsize == 32 and RESULT.itemsize == 48 and CONFIG.itemsize == 72 and STATS.itemsize == 32
 
 
 def make_trace(count: int, lo: int, hi: int, rate_per_s: float, seed: int, factor: int = 4) -> np.ndarray:
@@ -56,12 +56,14 @@ def release_arena() -> None:
 
 def run(requests: np.ndarray, budget_bytes: int, streams: int = 4, max_batch_requests: int = 4096,
         max_batch_keys: int = 1 << 26, plain_range_bits: int = 0, verify: bool = False, simulate: bool = False,
-        sim_overhead_s: float = 20e-6, sim_keys_per_s: float = 2e11, arena=None):
+        sim_overhead_s: float = 20e-6, sim_keys_per_s: float = 2e11, arena=None, outputs=None):
     """Run the trace; returns (results array, stats dict).
 
     The arena is ``arena`` (a uint8 device tensor of at least budget_bytes)
     or a torch allocation cached across calls; nothing is allocated when
-    ``simulate`` is set."""
+    ``simulate`` is set.  ``outputs``: None, or one device int32/uint32 tensor
+    (or None) per request, at least n long, that receives the request's
+    sorted keys."""
     requests = np.ascontiguousarray(requests, dtype=REQUEST)
     res = np.zeros(max(len(requests), 1), dtype=RESULT)
     cfg = np.zeros(1, dtype=CONFIG)
@@ -80,6 +82,18 @@ def run(requests: np.ndarray, budget_bytes: int, streams: int = 4, max_batch_req
     cfg["simulate"] = int(simulate)
     cfg["sim_overhead_s"] = sim_overhead_s
     cfg["sim_keys_per_s"] = sim_keys_per_s
+    ptrs = None
+    if outputs is not None:
+        if len(outputs) != len(requests):
+            raise ValueError("outputs needs one entry per request")
+        ptrs = np.zeros(max(len(requests), 1), dtype=np.uint64)
+        for i, t in enumerate(outputs):
+            if t is None:
+                continue
+            if not t.is_cuda or not t.is_contiguous() or t.element_size() != 4 or t.numel() < int(requests["n"][i]):
+                raise ValueError(f"outputs[{i}] must be a contiguous 4-byte device tensor of at least n elements")
+            ptrs[i] = t.data_ptr()
+        cfg["outputs"] = ptrs.ctypes.data
     st = np.zeros(1, dtype=STATS)
     _lib.check(_lib.bitsort_serve_run(requests.ctypes.data, len(requests), cfg.ctypes.data, res.ctypes.data,
                                       st.ctypes.data), "bitsort_serve_run")

@@ -1,4 +1,6 @@
 """Parity of the segmented batch path (bitsort_batch_u32) with the oracle."""
+import os
+
 import numpy as np
 import pytest
 
@@ -85,10 +87,13 @@ def test_out_of_range_and_bad_segment(o):
     assert flags[2] == bs.STATUS_BAD_SEGMENT and counts[2] == 0
 
 
-def test_batch_workload_sampled(o):
+def test_batch_workload_every_segment(o):
     """4096 segments, sizes log-uniform in [256, 2^20], range 4n rounded up to
-    a power of two: the full batch runs on the GPU; every 64th segment and the
-    ten largest are checked against the oracle on host-generated keys."""
+    a power of two: the full batch runs on the GPU, and every segment is
+    regenerated on the host and checked element by element against the
+    oracle's sort of it (its input as well)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import torch
     import paper_1312_0138_amd as bs
     count, seed = 4096, inputs.config_seed(4, 0)
@@ -98,7 +103,7 @@ def test_batch_workload_sampled(o):
     offsets[1:] = np.cumsum(sizes)
     total = int(offsets[-1])
     k = torch.empty(total, dtype=torch.int32, device="cuda")
-    for i in range(count):  # device generator fills the batch; sampled segments are re-made on the host
+    for i in range(count):  # the device generator fills the batch; the host re-makes every segment
         lo, hi = int(offsets[i]), int(offsets[i + 1])
         bs.generate(hi - lo, int(rbits[i]), inputs.segment_seed(seed, i), out=k[lo:hi])
     out = torch.empty_like(k)
@@ -106,11 +111,17 @@ def test_batch_workload_sampled(o):
     flags, counts = bs.batch_status(count)
     assert not flags.any()
     np.testing.assert_array_equal(counts, sizes.astype(np.uint64))
-    sample = sorted(set(range(0, count, 64)) | set(np.argsort(sizes)[-10:].tolist()))
-    got_all = to_np(out)
-    for i in sample:
+    keys_all, got_all = to_np(k), to_np(out)
+
+    def check(i):
         lo, hi = int(offsets[i]), int(offsets[i + 1])
         host_keys = inputs.distinct_uniform(hi - lo, int(rbits[i]), inputs.segment_seed(seed, i))
-        np.testing.assert_array_equal(to_np(k[lo:hi]), host_keys)
         want, _, _ = o.bitmap_sort(host_keys, int(rbits[i]))
-        np.testing.assert_array_equal(got_all[lo:hi], want, err_msg=f"segment {i}")
+        return (np.array_equal(keys_all[lo:hi], host_keys), np.array_equal(got_all[lo:hi], want))
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        res = list(ex.map(check, range(count)))
+    bad_in = [i for i, (a, _) in enumerate(res) if not a]
+    bad_out = [i for i, (_, b) in enumerate(res) if not b]
+    assert not bad_in, f"device-generated input differs from the host's in segments {bad_in[:10]}"
+    assert not bad_out, f"{len(bad_out)} segments differ from the oracle, first {bad_out[:10]}"

@@ -341,6 +341,36 @@ def test_duplicates_collapse(o, n, rb):
     np.testing.assert_array_equal(got[: want.size], want)
 
 
+def test_status_read_runs_the_pending_finish_once(o):
+    """A two-kernel sort leaves its totals to the status read: reading the
+    status after repeated keys compacts out[0..d) once, a second read (on the
+    stream, or on the caller's workspace) returns the same status and leaves
+    the output as it is."""
+    import torch
+    import paper_1312_0138_amd as bs
+    base = inputs.distinct_uniform(300_000, 24, 44)
+    rng = np.random.default_rng(4)
+    keys = base.copy()
+    at = rng.choice(keys.size, size=3000, replace=False)
+    keys[at] = base[rng.integers(0, keys.size, size=at.size)]
+    want, flags, _ = o.bitmap_sort(keys, 24)
+    assert flags == oracle.FLAG_DUPLICATE
+    k = to_dev(keys)
+    out = bs.sort(k, 24)
+    st1 = bs.status()
+    first = to_np(out).copy()
+    st2 = bs.status()
+    assert (st1.flags, st1.count) == (st2.flags, st2.count) == (2, want.size)
+    np.testing.assert_array_equal(first[: want.size], want)
+    np.testing.assert_array_equal(to_np(out), first)
+    ws = torch.empty(bs.workspace_bytes(keys.size, 24), dtype=torch.uint8, device="cuda")
+    out2 = bs.sort_ws(k, 24, ws)
+    a = bs.workspace_status(ws)
+    b = bs.workspace_status(ws)
+    assert (a.flags, a.count) == (b.flags, b.count) == (2, want.size)
+    np.testing.assert_array_equal(to_np(out2)[: want.size], want)
+
+
 def test_in_place_and_misaligned(o):
     import torch
     import paper_1312_0138_amd as bs

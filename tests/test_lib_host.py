@@ -58,6 +58,14 @@ def test_host_argument_checks(lib):
         E.BITSORT_ERR_TOO_LARGE
     assert E.bitsort_batch_ptr_u32(kp.ctypes.data, nn.ctypes.data, rb.ctypes.data, op.ctypes.data, 0, 0) == \
         E.BITSORT_ERR_INVALID_ARG
+    # 2^20 + 1 empty arrays of range 2^32 plan 4096 slices each: 2^32 + 4096
+    # slices in all, past the launch limit; rejected on the host before any
+    # device call (the slice total would wrap in 32 bits)
+    m = (1 << 20) + 1
+    zeros = np.zeros(m, dtype=np.uint64)
+    wide = np.full(m, 32, dtype=np.uint8)
+    assert E.bitsort_batch_ptr_u32(zeros.ctypes.data, zeros.ctypes.data, wide.ctypes.data, zeros.ctypes.data, m,
+                                   0) == E.BITSORT_ERR_TOO_LARGE
     assert E.bitsort_count_u32(fake, 100, 20, fake + 4, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_i32(fake, 10, 33, fake + 4096, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_radix_i32(fake, 100, fake + 4, 0) == E.BITSORT_ERR_INVALID_ARG
