@@ -10,7 +10,13 @@ whole-job throughput (Gkeys/s), the dominant kernel's roofline against the
 8 TB/s HBM3E peak (its duration measured with HIP events on its own stream),
 and the CPU oracle timed on this host's cores as a reported baseline.
 
-Workloads (default: plain-uniform):
+With no --workload, the headline is plain-small (10^6 keys, the workload the
+roofline target is set on) and the same JSON line carries, under "extras",
+plain-uniform (value and roofline fractions), the batch workload (one batched
+launch against 4096 plain launches, identical results) and the serving trace
+(throughput, p50/p99 latency); --no-extras leaves them out.
+
+Workloads:
   plain-uniform   2^26 distinct keys uniform without replacement in [0, 2^28)
   plain-small     10^6 distinct keys in [0, 2^24)
   plain-clustered keys from 64 Gaussian clusters (sigma 2^16) in [0, 2^28)
@@ -102,6 +108,15 @@ def algorithmic_bytes(n: int, rb: int, emit_path: str) -> dict:
     else:
         ab.update({"k_slice": r8 + 4 * n})
     return ab
+
+
+def atomic_algorithmic_bytes(n: int, rb: int) -> dict:
+    """The same method's bytes on the atomic-mark path: the mark reads the
+    keys (4n), the chunk counts make the bit-vector pass (R/8), the emission
+    writes the keys (4n); its second read of the bit-vector is overhead."""
+    r8 = max(1 << rb, 1 << 15) // 8
+    return {"k_mark_atomic": 4 * n, "k_chunk_count": r8, "k_chunk_scan": 0, "k_emit": 4 * n,
+            "path": 4 * n + (1 << rb) // 8 + 4 * n}
 
 
 def radix_algorithmic_bytes(n: int, key_bits: int, elem_bytes: int = 4) -> dict:
@@ -213,6 +228,7 @@ def sort_fn(bs, sorter):
     """The library call a step makes: fn(input buffer, rb, output buffer)."""
     return {
         "bitmap": lambda x, rb, out: bs.sort(x, rb, out),
+        "atomic": lambda x, rb, out: bs.sort_atomic(x, rb, out),
         "signed": lambda x, rb, out: bs.sort_signed(x, rb, out),
         "count": lambda x, rb, out: bs.sort_multiset(x, rb, out),
         "radix": lambda x, rb, out: bs.radix_sort(x, rb, out),
@@ -232,6 +248,7 @@ def oracle_fn(o, sorter, rb):
         return signed
     return {
         "bitmap": lambda keys: o.bitmap_sort(keys, rb)[0],
+        "atomic": lambda keys: o.bitmap_sort(keys, rb)[0],
         "count": lambda keys: o.counting_sort(keys, rb)[0],
         "radix": lambda keys: o.bitwise_sort1(keys, rb),
         "radix64": lambda keys: o.bitwise_sort1_u64(keys, rb),
@@ -241,6 +258,7 @@ def oracle_fn(o, sorter, rb):
 
 ORACLE_KIND = {
     "bitmap": "single-threaded C oracle (bitmap sort)",
+    "atomic": "single-threaded C oracle (bitmap sort)",
     "signed": "single-threaded C oracle (bitmap sort of the shifted keys)",
     "count": "single-threaded C oracle (counting sort)",
     "radix": "single-threaded C oracle (Algorithm 1, one-bit passes)",
@@ -259,7 +277,11 @@ def bench_plain(args, workload):
     spec = PLAIN[workload]
     rb = spec["rb"]
     sorter = spec.get("sorter", "bitmap")
-    bitmap_like = sorter in ("bitmap", "signed")
+    if getattr(args, "mark", "partition") == "atomic":
+        if sorter != "bitmap":
+            raise SystemExit("--mark atomic applies to the unsigned bitmap workloads")
+        sorter = "atomic"
+    bitmap_like = sorter in ("bitmap", "signed", "atomic")
     radix = sorter in ("radix", "radix64", "pairs")
     sort = sort_fn(bs, sorter)
     torch.cuda.set_device(0)
@@ -336,6 +358,8 @@ def bench_plain(args, workload):
         ab = radix_algorithmic_bytes(n, rb, elem)
     elif sorter == "count":
         ab = count_algorithmic_bytes(n, rb)
+    elif sorter == "atomic":
+        ab = atomic_algorithmic_bytes(n, rb)
     else:
         ab = algorithmic_bytes(n, rb, plan["emit_path"])
     kernels = {k: {"launches": int(l), "avg_us": round(1e3 * ms / max(l, 1), 3)} for k, (l, ms) in prof.items()}
@@ -347,7 +371,10 @@ def bench_plain(args, workload):
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 "traffic": read_traffic(dom, workload, digest), "algorithmic_bytes": ab[dom]}
     path_gbps = ab["path"] / (ms_per_step / 1e3) / 1e9
-    if bitmap_like:
+    if sorter == "atomic":
+        config = {"workload": workload, "description": spec["desc"], "n": n, "range_bits": rb,
+                  "input_pool": len(bufs), "mark": "atomic OR into the HBM bit-vector (bitsort_u32_atomic)"}
+    elif bitmap_like:
         config = {"workload": workload, "description": spec["desc"], "n": n, "range_bits": rb,
                   "input_pool": len(bufs), "slice_bits": plan["slice_bits"], "tile_log2": plan["tile_log2"],
                   "slices": plan["buckets"], "emit_path": plan["emit_path"]}
@@ -520,7 +547,7 @@ def serve_cpu_baseline(trace, results, budget_s: float = 20.0, max_keys: int = 1
     return keys_done / t_sort / 1e9, checked, keys_done, t_sort, bad
 
 
-def bench_serve(args):
+def bench_serve(args, oracle_check_s: float = 20.0):
     import math
 
     import numpy as np
@@ -569,14 +596,16 @@ def bench_serve(args):
                         "burst_over_one_by_one": round(t_burst / t_one, 3), "requests": 512},
         "verify_run": {"all_counts_and_flags_ok": ok, "gkeys_per_s": round(st_v["keys"] / st_v["makespan_s"] / 1e9, 3)},
     }
+    gk, checked, keys_done, t_sort, bad = serve_cpu_baseline(trace, res_v, budget_s=oracle_check_s)
+    sample = (f"{checked} requests of the trace ({keys_done} keys) sorted by the oracle, "
+              f"{t_sort:.2f} s; inputs regenerated on the host")
     if not args.no_cpu_baseline:
-        gk, checked, keys_done, t_sort, bad = serve_cpu_baseline(trace, res_v)
         out["cpu_baseline"] = {"value": round(gk, 4), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-                               "sample": f"{checked} requests of the trace ({keys_done} keys) sorted by the oracle, "
-                                         f"{t_sort:.2f} s; inputs regenerated on the host"}
-        out["oracle_digests_match"] = not bad
-        if bad:
-            out["oracle_mismatch_requests"] = bad[:20]
+                               "sample": sample}
+    out["oracle_sample"] = sample
+    out["oracle_digests_match"] = not bad
+    if bad:
+        out["oracle_mismatch_requests"] = bad[:20]
     return out
 
 
@@ -609,13 +638,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="plain-uniform", choices=sorted(PLAIN) + ["batch", "serve", "copy-calibration"])
+    ap.add_argument("--workload", default=None, choices=sorted(PLAIN) + ["batch", "serve", "copy-calibration"],
+                    help="one workload only (default: plain-small plus the extras)")
+    ap.add_argument("--no-extras", action="store_true", help="default run: the headline workload only")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--pool", type=int, default=0, help="input buffers to rotate through (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", default="", help="slice_bits,tile_log2,emit_path (0 = library choice)")
     ap.add_argument("--graph", action="store_true", help="time HIP-graph replays instead of eager calls")
+    ap.add_argument("--mark", default="partition", choices=["partition", "atomic"],
+                    help="bitmap workloads: the partitioned LDS mark (default) or the atomic-OR HBM mark")
     ap.add_argument("--autotune", action="store_true", help="run the autotuner for the workload first")
     args = ap.parse_args()
     if args.tune:
@@ -624,7 +657,11 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
-    if args.workload == "batch":
+    if args.workload is None:
+        result = bench_plain(args, "plain-small")
+        if not args.no_extras:
+            result["extras"] = bench_extras(args)
+    elif args.workload == "batch":
         result = bench_batch(args)
     elif args.workload == "serve":
         result = bench_serve(args)
@@ -633,6 +670,53 @@ def main():
     else:
         result = bench_plain(args, args.workload)
     print(json.dumps(result), flush=True)
+
+
+def bench_extras(args):
+    """The rest of the metric beside the headline: the 2^26-key workload, the
+    batch against per-array launches, and the serving trace (each its own
+    run; CPU baselines left to the single-workload runs)."""
+    import copy
+    sub = copy.copy(args)
+    sub.no_cpu_baseline = True
+    sub.autotune = False
+    sub.graph = False
+    sub.steps = max(10, min(args.steps, 50))
+    sub.warmup = max(2, min(args.warmup, 5))
+    t0 = time.perf_counter()
+    big = bench_plain(sub, "plain-uniform")
+    print(f"extras: plain-uniform done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    atomic = {}
+    for wl in ("plain-small", "plain-uniform"):
+        t0 = time.perf_counter()
+        sub_a = copy.copy(sub)
+        sub_a.mark = "atomic"
+        r = bench_plain(sub_a, wl)
+        atomic[wl] = {"value": r["value"], "unit": "Gkeys/s", "ms_per_step": r["ms_per_step"],
+                      "roofline": r["roofline"], "roofline_path": r["roofline_path"], "kernels": r["kernels"]}
+        print(f"extras: atomic {wl} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    batch = bench_batch(sub)
+    print(f"extras: batch done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    srv = bench_serve(sub, oracle_check_s=5.0)
+    print(f"extras: serve done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    return {
+        "plain-uniform": {"value": big["value"], "unit": "Gkeys/s", "ms_per_step": big["ms_per_step"],
+                          "steps": big["steps"], "config": big["config"], "roofline": big["roofline"],
+                          "roofline_path": big["roofline_path"], "kernels": big["kernels"]},
+        "atomic_mark": atomic,
+        "batch": {"value": batch["value"], "unit": "Gkeys/s", "config": batch["config"],
+                  "batched": batch["batched"], "batched_graph": batch["batched_graph"],
+                  "plain_loop": batch["plain_loop"], "pointer_array": batch["pointer_array"],
+                  "batched_over_plain": batch["batched_over_plain"],
+                  "identical_results": batch["identical_results"], "roofline_path": batch["roofline_path"]},
+        "serve": {"value": srv["value"], "unit": "Gkeys/s", "config": srv["config"],
+                  "latency_ms": srv["latency_ms"], "launches": srv["launches"],
+                  "calibration": srv["calibration"], "verify_run": srv["verify_run"],
+                  "oracle_digests_match": srv.get("oracle_digests_match"),
+                  "oracle_sample": srv.get("oracle_sample")},
+    }
 
 
 if __name__ == "__main__":

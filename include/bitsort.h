@@ -55,6 +55,7 @@ typedef void *bitsort_stream_t; /* a hipStream_t */
 #define BITSORT_STATUS_OUT_OF_RANGE 1u /* some key was >= 2^range_bits and was dropped */
 #define BITSORT_STATUS_DUPLICATE 2u    /* some key occurred more than once */
 #define BITSORT_STATUS_TIMEOUT 32u     /* a bounded wait between workgroups gave up: the output is invalid */
+#define BITSORT_STATUS_BAD_STATE 64u   /* bitsort_u32_atomic found its bit-vector not all zero: nothing written */
 
 typedef struct bitsort_status {
     uint32_t flags;  /* BITSORT_STATUS_* bits */
@@ -84,6 +85,47 @@ const char *bitsort_error_string(int code);
  */
 int bitsort_u32(const uint32_t *keys, uint64_t n, uint32_t range_bits, uint32_t *out,
                 bitsort_stream_t stream);
+
+/*
+ * The same sort as bitsort_u32, done the direct way: every key ORs its bit
+ * into a bit-vector kept in HBM with an atomic OR (Table I: OR-ing a 1 sets a
+ * bit, in any order and any number of times; the word index by a right shift,
+ * Example 3; the mask by a left shift, Example 2), lanes of a wave holding
+ * keys of the same word first combining their masks so that one atomic per
+ * word and wave is issued; then the ones of every 1024-word chunk are counted
+ * (Example 6), a device-wide exclusive prefix of the counts taken, and the set
+ * bits written out lowest first (Example 1) into out.  Arguments, errors and
+ * result as bitsort_u32 (repeated keys collapse into one; the status, read
+ * with bitsort_get_status on the same stream, flags them).  Its bit-vector
+ * (2^range_bits / 8 bytes, at least 4 KiB) is allocated per (device, stream),
+ * zeroed once, and left zero by every call: the emission clears the words it
+ * reads.  Four launches: mark, chunk counts, prefix, emission.
+ */
+int bitsort_u32_atomic(const uint32_t *keys, uint64_t n, uint32_t range_bits, uint32_t *out,
+                       bitsort_stream_t stream);
+
+/*
+ * The bitmap sort for 64-bit keys (Algorithm 1 of Section V is written for
+ * any integer type T; the result is again the ascending arrangement of
+ * Theorem 1): n distinct uint64 keys, each < 2^range_bits, range_bits 0..36,
+ * ascending into out.  The range is cut into 2^(range_bits - 32) groups of
+ * 2^32 keys by the bits above bit 31 (one group when range_bits <= 32); the
+ * keys' low 32 bits are gathered group by group, each group is sorted by the
+ * plain path's kernels (all groups in one pointer-array launch: mark into LDS
+ * slices by shift and OR, Table I and Examples 2-3; count, Example 6; emit,
+ * Example 1), and the groups are written back as 64-bit keys in order.
+ *   keys, out   device, n uint64 each; out == keys allowed, any other overlap
+ *               is rejected.
+ *   n           n < 2^32 and n <= 2^range_bits.
+ * Status with bitsort_get_status on the same stream: count = distinct keys
+ * written, OUT_OF_RANGE / DUPLICATE as for bitsort_u32; out[0 .. count) holds
+ * them ascending.  The call waits on the host once, after the grouping, for
+ * the groups' sizes (they plan the pointer-array launch).  Workspace: the
+ * stream's (about 4n bytes plus small tables) and its batch workspace.
+ * Errors: BITSORT_ERR_INVALID_ARG (range_bits > 36, null pointers, partial
+ * overlap), BITSORT_ERR_TOO_LARGE, BITSORT_ERR_NO_MEMORY, BITSORT_ERR_HIP.
+ */
+int bitsort_u64(const uint64_t *keys, uint64_t n, uint32_t range_bits, uint64_t *out, bitsort_stream_t stream);
 
 /*
  * The same bitmap sort for signed keys (the paper sorts any integer type,
@@ -135,8 +177,29 @@ int bitsort_u32_noalloc(const uint32_t *keys, uint64_t n, uint32_t range_bits, u
                         bitsort_status_t *status, bitsort_stream_t stream);
 
 /* Synchronise `stream`, then copy the status of the last call made on it
- * (library workspace) into *status. */
+ * (library workspace) into *status.  A two-kernel plain sort leaves its totals
+ * (flags, count, and after a repeated key the compaction of out[0 .. d)) to
+ * this read, which runs them on `stream` before it copies: read the status
+ * before using out when the input may hold a repeated key.  The same holds
+ * for bitsort_workspace_status and bitsort_graph_status. */
 int bitsort_get_status(bitsort_stream_t stream, bitsort_status_t *status);
+
+/*
+ * Give the library a workspace for the calls on `stream` (bitsort_u32,
+ * bitsort_i32, bitsort_count_u32 and the radix sorts), instead of the memory
+ * it would allocate and keep for that stream.
+ *   workspace  device pointer, 256-byte aligned, or NULL: the library
+ *              allocates its own again on the next call that needs it.
+ *   bytes      its size (at least 256); a later call whose workspace
+ *              (bitsort_workspace_bytes, bitsort_radix_workspace_bytes) is
+ *              larger returns BITSORT_ERR_NO_MEMORY and allocates nothing.
+ * The caller owns the memory, keeps it alive and leaves it alone while work
+ * enqueued on `stream` may still use it; the library never frees it.  A
+ * workspace the library had allocated for the stream is freed here (after
+ * synchronising `stream`).  The status of calls made before this one can no
+ * longer be read.
+ */
+int bitsort_set_workspace(void *workspace, size_t bytes, bitsort_stream_t stream);
 
 /* Synchronise `stream`, then copy the status held in a caller workspace. */
 int bitsort_workspace_status(const void *workspace, bitsort_stream_t stream,
@@ -144,7 +207,9 @@ int bitsort_workspace_status(const void *workspace, bitsort_stream_t stream,
 
 /*
  * Segmented sort: num_segments independent arrays sorted by one persistent
- * launch (each segment is the problem of bitsort_u32 with its own range).
+ * launch (each segment is the problem of bitsort_u32 with its own range: the
+ * ascending arrangement of Section IV and Theorem 1, by the marking of Table I
+ * and Examples 2-3, the counting of Example 6 and the bit test of Example 1).
  *   keys          device uint32, offsets[num_segments] elements in all.
  *   offsets       device uint64[num_segments + 1]; offsets[0] = 0 and
  *                 non-decreasing; segment s is keys[offsets[s] .. offsets[s+1]).
@@ -173,8 +238,44 @@ int bitsort_batch_u32(const uint32_t *keys, const uint64_t *offsets, uint32_t nu
 int bitsort_batch_status(bitsort_stream_t stream, bitsort_status_t *status, uint32_t num_segments);
 
 /*
+ * The segmented sort in two steps, for callers that capture the sort into
+ * their own HIP graph or must not allocate while it runs.  The problem is
+ * bitsort_batch_u32's (Section IV, Theorem 1, per segment).
+ *
+ * bitsort_batch_plan checks the segments on the host and sets up the work:
+ *   offsets     HOST uint64[num_segments + 1], offsets[0] = 0, non-decreasing.
+ *   range_bits  HOST uint8[num_segments], each 0..BITSORT_BATCH_MAX_RANGE_BITS,
+ *               with offsets[s+1] - offsets[s] <= 2^range_bits[s].
+ *   plan        receives the plan; it owns a device workspace (allocated here,
+ *               on the current device, freed by bitsort_batch_plan_destroy).
+ * Errors: BITSORT_ERR_INVALID_ARG (null pointers, num_segments out of
+ * 1..BITSORT_BATCH_MAX_SEGMENTS, offsets[0] != 0, a decreasing offset, a
+ * width above the limit), BITSORT_ERR_TOO_LARGE (a segment longer than its
+ * range, 2^40 keys or more in all), BITSORT_ERR_NO_MEMORY.
+ *
+ * bitsort_batch_run enqueues the sort: keys/out as bitsort_batch_u32 (the
+ * plan's offsets[num_segments] elements each, no overlap), offsets and
+ * range_bits the DEVICE copies of the arrays given to the plan.  It allocates
+ * nothing and makes no memset or host synchronisation, so it can be stream-
+ * captured; runs of one plan share its workspace and must not overlap in
+ * time.  Call on the plan's device.  bitsort_batch_plan_status synchronises
+ * `stream` and copies the per-segment statuses of the plan's last run (count
+ * <= num_segments).
+ */
+typedef struct bitsort_batch_plan bitsort_batch_plan_t;
+int bitsort_batch_plan(const uint64_t *offsets, const uint8_t *range_bits, uint32_t num_segments,
+                       bitsort_batch_plan_t **plan);
+int bitsort_batch_run(const bitsort_batch_plan_t *plan, const uint32_t *keys, const uint64_t *offsets,
+                      const uint8_t *range_bits, uint32_t *out, bitsort_stream_t stream);
+int bitsort_batch_plan_status(const bitsort_batch_plan_t *plan, bitsort_stream_t stream, bitsort_status_t *status,
+                              uint32_t count);
+int bitsort_batch_plan_destroy(bitsort_batch_plan_t *plan);
+
+/*
  * Pointer-array batch: count independent arrays, each sorted by the plain
- * path's method (partition into LDS slices, mark, scan, emit), all arrays in
+ * path's method (partition into LDS slices, mark by shift and OR -- Table I,
+ * Examples 2-3 --, count ones -- Example 6 --, emit set bits -- Example 1),
+ * each array's result its ascending arrangement (Theorem 1), all arrays in
  * one launch of each kernel -- any range_bits up to 32 per array, and every
  * key read once by the partition (the segmented launch above reads a segment
  * once per 2^20-bit slice of its range).  An array emits from LDS, or, when
@@ -336,7 +437,10 @@ int bitsort_plan_info(uint64_t n, uint32_t range_bits, uint32_t *slice_bits, uin
 
 /*
  * HIP graphs: the launches of one sort (plain or batch) captured once and
- * replayed on any stream with bitsort_graph_launch().  The device buffers are
+ * replayed on any stream with bitsort_graph_launch().  Each replay computes
+ * what bitsort_u32 or bitsort_batch_u32 computes (Section IV, Theorem 1: the
+ * ascending arrangement; marking by Table I and Examples 2-3, counting by
+ * Example 6, emission by Example 1).  The device buffers are
  * fixed at creation; their contents may change between replays (a batch is
  * re-planned on the device at every replay).  A graph owns its workspace, so
  * replays allocate nothing.  Replays of one graph must not overlap in time.

@@ -18,7 +18,7 @@ __all__ = [
     "plan_info", "BitsortError", "Status", "STATUS_OUT_OF_RANGE", "STATUS_DUPLICATE",
     "STATUS_BAD_SEGMENT", "Graph", "autotune", "autotune_batch", "tuning_save", "tuning_load",
     "tuning_clear", "radix_sort", "radix_workspace_bytes", "radix_sort_ws", "STATUS_TIMEOUT", "sort_signed", "radix_sort_signed", "sort_multiset", "radix_sort_u64",
-    "radix_sort_pairs", "sort_many",
+    "radix_sort_pairs", "sort_many", "BatchPlan", "set_workspace", "sort_atomic", "sort_u64",
 ]
 
 
@@ -55,6 +55,37 @@ def sort(keys, range_bits: int, out=None, stream=None):
         raise ValueError("out must have as many elements as keys")
     _lib.check(_lib.bitsort_u32(keys.data_ptr(), keys.numel(), range_bits, out.data_ptr(), _stream(stream)),
                "bitsort_u32")
+    return out
+
+
+def sort_atomic(keys, range_bits: int, out=None, stream=None):
+    """``sort`` through the bit-vector marked in HBM with atomic ORs
+    (bitsort_u32_atomic); status with ``status()``."""
+    torch = _torch()
+    _check_u32(keys, "keys")
+    if out is None:
+        out = torch.empty_like(keys)
+    _check_u32(out, "out")
+    if out.numel() != keys.numel():
+        raise ValueError("out must have as many elements as keys")
+    _lib.check(_lib.bitsort_u32_atomic(keys.data_ptr(), keys.numel(), range_bits, out.data_ptr(), _stream(stream)),
+               "bitsort_u32_atomic")
+    return out
+
+
+def sort_u64(keys, range_bits: int, out=None, stream=None):
+    """Bitmap sort of distinct 64-bit keys below 2^range_bits (range_bits <=
+    36): an int64/uint64 device tensor; returns ``out``; status with
+    ``status()``."""
+    torch = _torch()
+    if keys.dtype not in (torch.int64, torch.uint64) or not keys.is_cuda or not keys.is_contiguous():
+        raise TypeError("keys must be a contiguous 64-bit device tensor")
+    if out is None:
+        out = torch.empty_like(keys)
+    if out.dtype != keys.dtype or not out.is_cuda or not out.is_contiguous() or out.numel() != keys.numel():
+        raise ValueError("out must be a contiguous 64-bit device tensor as long as keys")
+    _lib.check(_lib.bitsort_u64(keys.data_ptr(), keys.numel(), range_bits, out.data_ptr(), _stream(stream)),
+               "bitsort_u64")
     return out
 
 
@@ -245,6 +276,68 @@ def sort_many(arrays, range_bits, outs=None, stream=None):
     _lib.check(_lib.bitsort_batch_ptr_u32(kp.ctypes.data, nn.ctypes.data, rb.ctypes.data, op.ctypes.data, count,
                                           _stream(stream)), "bitsort_batch_ptr_u32")
     return outs
+
+
+class BatchPlan:
+    """Segments checked on the host once (``offsets``/``range_bits`` as numpy
+    or CPU arrays); ``run`` enqueues the segmented sort with the plan's own
+    workspace: it allocates nothing and can be captured into a HIP graph."""
+
+    def __init__(self, offsets, range_bits):
+        import numpy as np
+        self._off = np.ascontiguousarray(np.asarray(offsets), dtype=np.uint64)
+        self._rb = np.ascontiguousarray(np.asarray(range_bits), dtype=np.uint8)
+        self.segments = int(self._rb.size)
+        if self._off.size != self.segments + 1:
+            raise ValueError("offsets must have num_segments + 1 entries")
+        rc, h = _lib.bitsort_batch_plan(self._off.ctypes.data, self._rb.ctypes.data, self.segments)
+        _lib.check(rc, "bitsort_batch_plan")
+        self._h = h
+
+    def run(self, keys, offsets, range_bits, out, stream=None):
+        """``offsets``/``range_bits``: the device copies of the planned arrays."""
+        _check_u32(keys, "keys")
+        _check_u32(out, "out")
+        _lib.check(_lib.bitsort_batch_run(self._h, keys.data_ptr(), offsets.data_ptr(), range_bits.data_ptr(),
+                                          out.data_ptr(), _stream(stream)), "bitsort_batch_run")
+        return out
+
+    def status(self, stream=None):
+        import numpy as np
+        rc, arr = _lib.bitsort_batch_plan_status(self._h, _stream(stream), self.segments)
+        _lib.check(rc, "bitsort_batch_plan_status")
+        return (np.array([arr[i].flags for i in range(self.segments)], dtype=np.uint32),
+                np.array([arr[i].count for i in range(self.segments)], dtype=np.uint64))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.check(_lib.bitsort_batch_plan_destroy(self._h), "bitsort_batch_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+
+_WORKSPACES = {}
+
+
+def set_workspace(workspace, stream=None) -> None:
+    """Use a caller tensor (uint8, on the device) as the workspace of the calls
+    on ``stream``; None hands the choice back to the library.  The tensor is
+    kept alive here until it is replaced."""
+    sid = _stream(stream)
+    if workspace is None:
+        _lib.check(_lib.bitsort_set_workspace(None, 0, sid), "bitsort_set_workspace")
+        _WORKSPACES.pop(sid, None)
+        return
+    if not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
+    _lib.check(_lib.bitsort_set_workspace(workspace.data_ptr(), workspace.numel() * workspace.element_size(), sid),
+               "bitsort_set_workspace")
+    _WORKSPACES[sid] = workspace
 
 
 def batch_status(num_segments: int, stream=None):

@@ -21,6 +21,7 @@ STATUS_OUT_OF_RANGE = 1
 STATUS_DUPLICATE = 2
 STATUS_BAD_SEGMENT = 4
 STATUS_TIMEOUT = 32
+STATUS_BAD_STATE = 64
 REQ_REJECTED = 8
 REQ_INVALID = 16
 
@@ -57,6 +58,8 @@ _SIGS = {
     "bitsort_workspace_bytes": (_c.c_size_t, [_u64, _u32]),
     "bitsort_u32_ws": (_c.c_int, [_vp, _u64, _u32, _vp, _vp, _c.c_size_t, _vp]),
     "bitsort_u32_noalloc": (_c.c_int, [_vp, _u64, _u32, _vp, _vp, _vp]),
+    "bitsort_u32_atomic": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
+    "bitsort_u64": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
     "bitsort_radix_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
     "bitsort_radix_i32": (_c.c_int, [_vp, _u64, _vp, _vp]),
     "bitsort_radix_u64": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
@@ -70,6 +73,11 @@ _SIGS = {
     "bitsort_batch_u32": (_c.c_int, [_vp, _vp, _u32, _vp, _vp, _u64, _vp]),
     "bitsort_batch_status": (_c.c_int, [_vp, _c.POINTER(Status), _u32]),
     "bitsort_batch_ptr_u32": (_c.c_int, [_vp, _vp, _vp, _vp, _u32, _vp]),
+    "bitsort_batch_plan": (_c.c_int, [_vp, _vp, _u32, _c.POINTER(_vp)]),
+    "bitsort_batch_run": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "bitsort_batch_plan_status": (_c.c_int, [_vp, _vp, _c.POINTER(Status), _u32]),
+    "bitsort_batch_plan_destroy": (_c.c_int, [_vp]),
+    "bitsort_set_workspace": (_c.c_int, [_vp, _c.c_size_t, _vp]),
     "bitsort_generate_u32": (_c.c_int, [_vp, _u64, _u64, _u32, _u64, _vp]),
     "bitsort_debug_bitmap_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
     "bitsort_debug_prefix_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
@@ -147,6 +155,14 @@ def bitsort_u32(keys: int, n: int, range_bits: int, out: int, stream: int) -> in
     return lib().bitsort_u32(keys, n, range_bits, out, stream)
 
 
+def bitsort_u32_atomic(keys: int, n: int, range_bits: int, out: int, stream: int) -> int:
+    return lib().bitsort_u32_atomic(keys, n, range_bits, out, stream)
+
+
+def bitsort_u64(keys: int, n: int, range_bits: int, out: int, stream: int) -> int:
+    return lib().bitsort_u64(keys, n, range_bits, out, stream)
+
+
 def bitsort_workspace_bytes(n: int, range_bits: int) -> int:
     return lib().bitsort_workspace_bytes(n, range_bits)
 
@@ -199,6 +215,31 @@ def bitsort_radix_u32_ws(keys: int, n: int, key_bits: int, out: int, ws: int, ws
 def bitsort_batch_ptr_u32(keys: int, n: int, range_bits: int, out: int, count: int, stream: int) -> int:
     """keys/n/range_bits/out: addresses of host arrays (see the header)."""
     return lib().bitsort_batch_ptr_u32(keys, n, range_bits, out, count, stream)
+
+
+def bitsort_batch_plan(offsets: int, range_bits: int, num_segments: int):
+    """offsets / range_bits: addresses of HOST arrays; -> (rc, plan handle)."""
+    p = _vp()
+    rc = lib().bitsort_batch_plan(offsets, range_bits, num_segments, ctypes.byref(p))
+    return rc, p.value
+
+
+def bitsort_batch_run(plan: int, keys: int, offsets: int, range_bits: int, out: int, stream: int) -> int:
+    return lib().bitsort_batch_run(plan, keys, offsets, range_bits, out, stream)
+
+
+def bitsort_batch_plan_status(plan: int, stream: int, count: int):
+    arr = (Status * max(count, 1))()
+    rc = lib().bitsort_batch_plan_status(plan, stream, arr, count)
+    return rc, arr
+
+
+def bitsort_batch_plan_destroy(plan: int) -> int:
+    return lib().bitsort_batch_plan_destroy(plan)
+
+
+def bitsort_set_workspace(workspace: int, nbytes: int, stream: int) -> int:
+    return lib().bitsort_set_workspace(workspace, nbytes, stream)
 
 
 def bitsort_get_status(stream: int) -> tuple[int, Status]:

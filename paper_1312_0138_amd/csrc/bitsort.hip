@@ -89,6 +89,12 @@ namespace {
 #include "multi_kernels.inc"
 
 // ---------------------------------------------------------------------------
+#include "atomic_kernels.inc"
+
+// ---------------------------------------------------------------------------
+#include "wide_kernels.inc"
+
+// ---------------------------------------------------------------------------
 // Host side.
 
 struct Plan {
@@ -263,13 +269,14 @@ int launch_status() {
 // Kernel timing (bitsort_profile_*): events bracketing each launch.
 enum KernelId : int {
   kKPartition = 0, kKSlice, kKEmit, kKFinish, kKDirect, kKBatchPlan, kKBatchRun, kKRadixHist, kKRadixScan,
-  kKRadixPass, kKCountSlice, kKPartitionMulti, kKSliceMulti, kKEmitMulti, kKFinishMulti, kKCount
+  kKRadixPass, kKCountSlice, kKPartitionMulti, kKSliceMulti, kKEmitMulti, kKFinishMulti, kKMarkAtomic,
+  kKChunkCount, kKChunkScan, kKCount
 };
 const char* const kKernelNames[kKCount] = {"k_partition", "k_slice",      "k_emit",       "k_finish",
                                            "k_direct",    "k_batch_plan", "k_batch_run",  "k_radix_hist",
                                            "k_radix_scan", "k_radix_pass", "k_count_slice",
                                            "k_partition_multi", "k_slice_multi", "k_emit_multi",
-                                           "k_finish_multi"};
+                                           "k_finish_multi", "k_mark_atomic", "k_chunk_count", "k_chunk_scan"};
 struct PendingTiming {
   int kernel;
   hipEvent_t start, stop;
@@ -401,7 +408,7 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
   if (p.via_bitvec) {
     LaunchTimer timer(kKEmit, stream);
     hipLaunchKernelGGL((k_emit<kEmitBlock>), dim3(static_cast<uint32_t>(p.n_chunks)), dim3(kEmitBlock), 0, stream,
-                       bitvec, chunk_base, out, mode, dbg_prefix, 0u - p.bias);
+                       bitvec, chunk_base, out, mode, dbg_prefix, 0u - p.bias, nullptr);
     rc = launch_status();
     if (rc != BITSORT_OK || mode != kEmit) return rc;
   }
@@ -853,6 +860,7 @@ int run_radix(const RadixPlan& p, const K* keys, const uint32_t* vals, uint64_t 
 struct StreamCtx {
   void* ws = nullptr;
   size_t bytes = 0;
+  bool external = false;   // ws is the caller's (bitsort_set_workspace): never grown or freed here
   bool last_empty = true;  // last call had n == 0 (status is all zero)
   bool used = false;
   void* batch_ws = nullptr;
@@ -861,6 +869,9 @@ struct StreamCtx {
   void* desc_host = nullptr;        // pinned staging of bitsort_batch_ptr_u32's descriptors
   size_t desc_host_bytes = 0;
   hipEvent_t desc_copied = nullptr;  // the last descriptor upload has left desc_host
+  void* atomic_ws = nullptr;         // bitsort_u32_atomic's workspace: zero when allocated, kept zero
+  size_t atomic_bytes = 0;
+  bool last_atomic = false;          // the last call's status is in atomic_ws
 };
 std::mutex g_mu;
 std::map<std::pair<int, void*>, StreamCtx> g_ctx;
@@ -871,8 +882,9 @@ StreamCtx& ctx_for(bitsort_stream_t stream) {
   return g_ctx[{dev, stream}];
 }
 
-int grow(void** ptr, size_t* have, size_t need, hipStream_t stream) {
+int grow(void** ptr, size_t* have, size_t need, hipStream_t stream, bool external = false) {
   if (*have >= need && *ptr != nullptr) return BITSORT_OK;
+  if (external) return BITSORT_ERR_NO_MEMORY;  // the caller's workspace is too small: no allocation
   if (*ptr != nullptr) {
     if (hipStreamSynchronize(stream) != hipSuccess) return BITSORT_ERR_HIP;
     if (hipFree(*ptr) != hipSuccess) return BITSORT_ERR_HIP;
@@ -948,10 +960,71 @@ int radix_on_stream(const K* keys, const uint32_t* vals, uint64_t n, uint32_t ke
   if ((rc = init_kernels()) != BITSORT_OK) return rc;
   RadixPlan p;
   make_radix_plan(n, key_bits, sizeof(K), PAIRS, &p);
-  rc = grow(&c.ws, &c.bytes, p.bytes, s);
+  rc = grow(&c.ws, &c.bytes, p.bytes, s, c.external);
   if (rc != BITSORT_OK) return rc;
   c.last_empty = false;
+  c.last_atomic = false;
   return run_radix<K, PAIRS>(p, keys, vals, n, key_bits, flip, out, vout, c.ws, s);
+}
+
+// ---- the bit-vector marked in HBM with atomics (bitsort_u32_atomic) ---------------
+
+// Workspace: [status + marked-key counter][chunk counts u32][chunk prefixes
+// u64][bit-vector, at least one 1024-word chunk], every part at the same
+// offset whatever the range (room for the counts and prefixes of a 2^32-bit
+// range), so that calls of different widths never write their counts into
+// words of another call's bit-vector.  Zeroed once when it is allocated;
+// each call leaves its bit-vector zero again (the emission clears the words
+// it read, k_chunk_scan the counter), so no call clears the bit-vector in a
+// pass of its own.
+struct AtomicPlan {
+  uint64_t words = 0, chunks = 0;
+  size_t off_counts = 0, off_base = 0, off_bitvec = 0, bytes = 0;
+};
+constexpr size_t kAtomicCounterOffset = 128;
+
+void make_atomic_plan(uint32_t rb, AtomicPlan* p) {
+  *p = AtomicPlan();
+  p->words = std::max<uint64_t>((1ull << rb) / 32u, kChunkWords);
+  p->chunks = p->words / kChunkWords;
+  constexpr uint64_t kMaxChunks = (1ull << 32) / 32u / kChunkWords;
+  p->off_counts = kHeaderBytes;
+  p->off_base = align256(p->off_counts + 4 * kMaxChunks);
+  p->off_bitvec = align256(p->off_base + 8 * kMaxChunks);
+  p->bytes = align256(p->off_bitvec + 4 * p->words);
+}
+
+int run_atomic(const AtomicPlan& p, const uint32_t* keys, uint64_t n, uint32_t rb, uint32_t* out, void* ws,
+               hipStream_t s) {
+  char* base = static_cast<char*>(ws);
+  auto* status = reinterpret_cast<Status*>(base);
+  auto* valid = reinterpret_cast<unsigned long long*>(base + kAtomicCounterOffset);
+  auto* counts = reinterpret_cast<uint32_t*>(base + p.off_counts);
+  auto* chunk_base = reinterpret_cast<uint64_t*>(base + p.off_base);
+  auto* bitvec = reinterpret_cast<uint32_t*>(base + p.off_bitvec);
+  const uint64_t per_block = static_cast<uint64_t>(kMarkBlock) * kMarkUnroll;
+  const uint64_t grid = std::min<uint64_t>((n + per_block - 1) / per_block, 8ull * device_cus());
+  {
+    LaunchTimer timer(kKMarkAtomic, s);
+    hipLaunchKernelGGL(k_mark_atomic<kMarkBlock>, dim3(static_cast<uint32_t>(grid)), dim3(kMarkBlock), 0, s, keys, n,
+                       1ull << rb, bitvec, valid);
+    if (launch_status() != BITSORT_OK) return BITSORT_ERR_HIP;
+  }
+  {
+    LaunchTimer timer(kKChunkCount, s);
+    hipLaunchKernelGGL(k_chunk_count, dim3(static_cast<uint32_t>(p.chunks)), dim3(256), 0, s, bitvec, counts);
+    if (launch_status() != BITSORT_OK) return BITSORT_ERR_HIP;
+  }
+  {
+    LaunchTimer timer(kKChunkScan, s);
+    hipLaunchKernelGGL(k_chunk_scan<1024>, dim3(1), dim3(1024), 0, s, counts, p.chunks, chunk_base, n, valid,
+                       status);
+    if (launch_status() != BITSORT_OK) return BITSORT_ERR_HIP;
+  }
+  LaunchTimer timer(kKEmit, s);
+  hipLaunchKernelGGL((k_emit<kEmitBlock>), dim3(static_cast<uint32_t>(p.chunks)), dim3(kEmitBlock), 0, s, bitvec,
+                     chunk_base, out, static_cast<int>(kEmit), nullptr, 0u, bitvec);
+  return launch_status();
 }
 
 #include "serve.inc"
@@ -986,6 +1059,103 @@ int noalloc_scratch_of_device(void** ptr) {
   return BITSORT_OK;
 }
 
+// Enqueue a pointer-array launch planned in p: its workspace is the stream's
+// batch workspace, its descriptors go up from the stream's pinned buffer.
+// Called with g_mu held.
+int multi_on_stream(StreamCtx& c, const MultiPlan& p, uint32_t count, hipStream_t s) {
+  int rc = grow(&c.batch_ws, &c.batch_bytes, p.bytes, s);
+  if (rc != BITSORT_OK) return rc;
+  c.batch_segments = count;
+  // Descriptors go up from a pinned buffer of the stream's own; before it is
+  // refilled, the previous upload from it must have finished.
+  const size_t dbytes = sizeof(MultiDesc) * count;
+  if (c.desc_copied != nullptr && hipEventSynchronize(c.desc_copied) != hipSuccess) return BITSORT_ERR_HIP;
+  if (c.desc_copied == nullptr && hipEventCreateWithFlags(&c.desc_copied, hipEventDisableTiming) != hipSuccess) {
+    c.desc_copied = nullptr;
+    return BITSORT_ERR_HIP;
+  }
+  if (c.desc_host_bytes < dbytes) {
+    if (c.desc_host != nullptr) (void)hipHostFree(c.desc_host);
+    c.desc_host = nullptr;
+    c.desc_host_bytes = 0;
+    if (hipHostMalloc(&c.desc_host, dbytes, hipHostMallocDefault) != hipSuccess) {
+      c.desc_host = nullptr;
+      return BITSORT_ERR_NO_MEMORY;
+    }
+    c.desc_host_bytes = dbytes;
+  }
+  std::memcpy(c.desc_host, p.desc.data(), dbytes);
+  if (hipMemcpyAsync(static_cast<char*>(c.batch_ws) + p.off_desc, c.desc_host, dbytes, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipEventRecord(c.desc_copied, s) != hipSuccess)
+    return BITSORT_ERR_HIP;
+  return run_multi(p, count, c.batch_ws, s);
+}
+
+
+// ---- uint64 keys over ranges up to 2^36 (bitsort_u64) -------------------------
+
+// Workspace of bitsort_u64 (the stream's plain workspace): [status][tile
+// table u32 nt x bins][tile starts u32 nt x bins][bin totals u64][group ->
+// array index i32][low 32-bit keys, n].  The pointer-array launch over the
+// groups uses the stream's batch workspace.
+int run_wide(StreamCtx& c, const uint64_t* keys, uint64_t n, uint32_t rb, uint64_t* out, hipStream_t s) {
+  const uint64_t nt = (n + kWideTile - 1) / kWideTile;
+  const size_t off_table = kHeaderBytes;
+  const size_t off_starts = align256(off_table + 4ull * nt * kWideBins);
+  const size_t off_totals = align256(off_starts + 4ull * nt * kWideBins);
+  const size_t off_present = align256(off_totals + 8ull * kWideBins);
+  const size_t off_low = align256(off_present + 4ull * kWideGroups);
+  const size_t bytes = align256(off_low + 4ull * n);
+  int rc = grow(&c.ws, &c.bytes, bytes, s, c.external);
+  if (rc != BITSORT_OK) return rc;
+  char* base = static_cast<char*>(c.ws);
+  auto* table = reinterpret_cast<uint32_t*>(base + off_table);
+  auto* starts = reinterpret_cast<uint32_t*>(base + off_starts);
+  auto* totals = reinterpret_cast<uint64_t*>(base + off_totals);
+  auto* present = reinterpret_cast<int32_t*>(base + off_present);
+  auto* low = reinterpret_cast<uint32_t*>(base + off_low);
+  hipLaunchKernelGGL(k_wide_count, dim3(static_cast<uint32_t>(nt)), dim3(kWideBlock), 0, s, keys, n, rb, table);
+  hipLaunchKernelGGL(k_wide_scan, dim3(kWideBins), dim3(1024), 0, s, table, nt, starts, totals);
+  hipLaunchKernelGGL(k_wide_split, dim3(static_cast<uint32_t>(nt)), dim3(kWideBlock), 0, s, keys, n, rb, starts,
+                     totals, low);
+  if ((rc = launch_status()) != BITSORT_OK) return rc;
+  // The groups' sizes plan the pointer-array launch: the host waits here.
+  uint64_t tot[kWideBins] = {};
+  if (hipMemcpyAsync(tot, totals, sizeof(tot), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return BITSORT_ERR_HIP;
+  std::vector<const uint32_t*> gk;
+  std::vector<uint32_t*> go;
+  std::vector<uint64_t> gn;
+  std::vector<uint8_t> grb;
+  int32_t idx[kWideGroups];
+  uint64_t kept = 0;
+  for (uint32_t g = 0; g < kWideGroups; ++g) {
+    idx[g] = -1;
+    if (tot[g] > 0) {
+      idx[g] = static_cast<int32_t>(gk.size());
+      gk.push_back(low + kept);
+      go.push_back(low + kept);  // sorted in place
+      gn.push_back(tot[g]);
+      grb.push_back(static_cast<uint8_t>(rb > 32 ? 32 : rb));
+    }
+    kept += tot[g];
+  }
+  if (hipMemcpy(present, idx, sizeof(idx), hipMemcpyHostToDevice) != hipSuccess) return BITSORT_ERR_HIP;
+  const SegStatus* seg = nullptr;
+  if (!gk.empty()) {
+    MultiPlan mp;
+    const uint32_t count = static_cast<uint32_t>(gk.size());
+    if ((rc = make_multi_plan(gk.data(), gn.data(), grb.data(), go.data(), count, &mp)) != BITSORT_OK) return rc;
+    if ((rc = multi_on_stream(c, mp, count, s)) != BITSORT_OK) return rc;
+    seg = reinterpret_cast<const SegStatus*>(static_cast<char*>(c.batch_ws) + mp.off_status);
+  }
+  const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((kept + 255) / 256, 8ull * device_cus()));
+  hipLaunchKernelGGL(k_wide_join, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, low, totals, present, seg,
+                     kept, out, reinterpret_cast<Status*>(base));
+  return launch_status();
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1074,10 +1244,37 @@ int bitsort_u32(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32_t*
   }
   Plan p;
   make_plan(n, range_bits, &p);
-  rc = grow(&c.ws, &c.bytes, p.bytes, s);
+  rc = grow(&c.ws, &c.bytes, p.bytes, s, c.external);
   if (rc != BITSORT_OK) return rc;
   c.last_empty = false;
+  c.last_atomic = false;
   return run_plain(p, keys, n, out, c.ws, s, kEmit, nullptr, nullptr, nullptr, true);
+}
+
+int bitsort_u32_atomic(const uint32_t* keys, uint64_t n, uint32_t range_bits, uint32_t* out,
+                       bitsort_stream_t stream) {
+  int rc = check_args(keys, n, range_bits, out);
+  if (rc != BITSORT_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  StreamCtx& c = ctx_for(stream);
+  c.used = true;
+  if (n == 0) {
+    c.last_empty = true;
+    return BITSORT_OK;
+  }
+  if ((rc = init_kernels()) != BITSORT_OK) return rc;
+  AtomicPlan p;
+  make_atomic_plan(range_bits, &p);
+  if (c.atomic_bytes < p.bytes || c.atomic_ws == nullptr) {
+    rc = grow(&c.atomic_ws, &c.atomic_bytes, p.bytes, s);
+    if (rc != BITSORT_OK) return rc;
+    // zero once, when allocated: the bit-vector and the counter are kept zero from here on
+    if (hipMemsetAsync(c.atomic_ws, 0, c.atomic_bytes, s) != hipSuccess) return BITSORT_ERR_HIP;
+  }
+  c.last_empty = false;
+  c.last_atomic = true;
+  return run_atomic(p, keys, n, range_bits, out, c.atomic_ws, s);
 }
 
 size_t bitsort_radix_workspace_bytes(uint64_t n, uint32_t key_bits) {
@@ -1123,9 +1320,10 @@ int bitsort_count_u32(const uint32_t* keys, uint64_t n, uint32_t range_bits, uin
   }
   Plan p;
   make_count_plan(n, range_bits, &p);
-  int rc = grow(&c.ws, &c.bytes, p.bytes, s);
+  int rc = grow(&c.ws, &c.bytes, p.bytes, s, c.external);
   if (rc != BITSORT_OK) return rc;
   c.last_empty = false;
+  c.last_atomic = false;
   return run_count(p, keys, n, out, c.ws, s);
 }
 
@@ -1163,9 +1361,10 @@ int bitsort_i32(const int32_t* keys_s, uint64_t n, uint32_t range_bits, int32_t*
   Plan p;
   make_plan(n, range_bits, &p);
   p.bias = range_bits ? (1u << (range_bits - 1)) : 0u;
-  rc = grow(&c.ws, &c.bytes, p.bytes, s);
+  rc = grow(&c.ws, &c.bytes, p.bytes, s, c.external);
   if (rc != BITSORT_OK) return rc;
   c.last_empty = false;
+  c.last_atomic = false;
   return run_plain(p, keys, n, out, c.ws, s, kEmit, nullptr, nullptr, nullptr, true);
 }
 
@@ -1182,7 +1381,7 @@ int bitsort_get_status(bitsort_stream_t stream, bitsort_status_t* status) {
       *status = bitsort_status_t{0, 0, 0};
       return BITSORT_OK;
     }
-    ws = c.ws;
+    ws = c.last_atomic ? c.atomic_ws : c.ws;
   }
   return read_plain_status(ws, s, status);
 }
@@ -1255,36 +1454,30 @@ int bitsort_batch_ptr_u32(const uint32_t* const* keys, const uint64_t* n, const 
   if (rc != BITSORT_OK) return rc;
   MultiPlan p;
   if ((rc = make_multi_plan(keys, n, range_bits, out, count, &p)) != BITSORT_OK) return rc;
+  std::lock_guard<std::mutex> lock(g_mu);
+  StreamCtx& c = ctx_for(stream);
+  return multi_on_stream(c, p, count, static_cast<hipStream_t>(stream));
+}
+
+int bitsort_u64(const uint64_t* keys, uint64_t n, uint32_t range_bits, uint64_t* out, bitsort_stream_t stream) {
+  if (range_bits > kWideMaxRangeBits) return BITSORT_ERR_INVALID_ARG;
+  if (n > 0 && (keys == nullptr || out == nullptr)) return BITSORT_ERR_INVALID_ARG;
+  if (n >= (1ull << 32) || n > (1ull << range_bits)) return BITSORT_ERR_TOO_LARGE;
+  if (n > 0 && static_cast<const void*>(keys) != static_cast<const void*>(out) && overlaps(keys, out, 8 * n))
+    return BITSORT_ERR_INVALID_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lock(g_mu);
   StreamCtx& c = ctx_for(stream);
-  rc = grow(&c.batch_ws, &c.batch_bytes, p.bytes, s);
+  c.used = true;
+  if (n == 0) {
+    c.last_empty = true;
+    return BITSORT_OK;
+  }
+  int rc = init_kernels();
   if (rc != BITSORT_OK) return rc;
-  c.batch_segments = count;
-  // Descriptors go up from a pinned buffer of the stream's own; before it is
-  // refilled, the previous upload from it must have finished.
-  const size_t dbytes = sizeof(MultiDesc) * count;
-  if (c.desc_copied != nullptr && hipEventSynchronize(c.desc_copied) != hipSuccess) return BITSORT_ERR_HIP;
-  if (c.desc_copied == nullptr && hipEventCreateWithFlags(&c.desc_copied, hipEventDisableTiming) != hipSuccess) {
-    c.desc_copied = nullptr;
-    return BITSORT_ERR_HIP;
-  }
-  if (c.desc_host_bytes < dbytes) {
-    if (c.desc_host != nullptr) (void)hipHostFree(c.desc_host);
-    c.desc_host = nullptr;
-    c.desc_host_bytes = 0;
-    if (hipHostMalloc(&c.desc_host, dbytes, hipHostMallocDefault) != hipSuccess) {
-      c.desc_host = nullptr;
-      return BITSORT_ERR_NO_MEMORY;
-    }
-    c.desc_host_bytes = dbytes;
-  }
-  std::memcpy(c.desc_host, p.desc.data(), dbytes);
-  if (hipMemcpyAsync(static_cast<char*>(c.batch_ws) + p.off_desc, c.desc_host, dbytes, hipMemcpyHostToDevice, s) !=
-          hipSuccess ||
-      hipEventRecord(c.desc_copied, s) != hipSuccess)
-    return BITSORT_ERR_HIP;
-  return run_multi(p, count, c.batch_ws, s);
+  c.last_empty = false;
+  c.last_atomic = false;
+  return run_wide(c, keys, n, range_bits, out, s);
 }
 
 int bitsort_batch_status(bitsort_stream_t stream, bitsort_status_t* status, uint32_t num_segments) {
@@ -1304,6 +1497,91 @@ int bitsort_batch_status(bitsort_stream_t stream, bitsort_status_t* status, uint
                 hipMemcpyDeviceToHost) != hipSuccess)
     return BITSORT_ERR_HIP;
   return BITSORT_OK;
+}
+
+int bitsort_set_workspace(void* workspace, size_t bytes, bitsort_stream_t stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (workspace != nullptr && ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0 || bytes < kHeaderBytes))
+    return BITSORT_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mu);
+  StreamCtx& c = ctx_for(stream);
+  if (c.ws != nullptr && !c.external) {  // the library's own allocation goes; earlier work on it must end first
+    if (hipStreamSynchronize(s) != hipSuccess || hipFree(c.ws) != hipSuccess) return BITSORT_ERR_HIP;
+  }
+  c.ws = workspace;
+  c.bytes = workspace != nullptr ? bytes : 0;
+  c.external = workspace != nullptr;
+  c.last_empty = true;  // the status of a call made before now is gone with the old workspace
+  return BITSORT_OK;
+}
+
+// ---- batch plans: host-checked segments, workspace fixed up front --------------
+
+struct bitsort_batch_plan {
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  uint32_t segments = 0;
+  uint64_t max_keys = 0;
+  BatchTuning tuning;
+  int device = 0;
+};
+
+int bitsort_batch_plan(const uint64_t* offsets, const uint8_t* range_bits, uint32_t num_segments,
+                       bitsort_batch_plan_t** plan) {
+  if (plan == nullptr) return BITSORT_ERR_INVALID_ARG;
+  *plan = nullptr;
+  if (offsets == nullptr || range_bits == nullptr || num_segments == 0 || num_segments > BITSORT_BATCH_MAX_SEGMENTS)
+    return BITSORT_ERR_INVALID_ARG;
+  if (offsets[0] != 0) return BITSORT_ERR_INVALID_ARG;
+  for (uint32_t i = 0; i < num_segments; ++i) {
+    if (range_bits[i] > kMaxBatchRangeBits || offsets[i + 1] < offsets[i]) return BITSORT_ERR_INVALID_ARG;
+    if (offsets[i + 1] - offsets[i] > (1ull << range_bits[i])) return BITSORT_ERR_TOO_LARGE;
+  }
+  if (offsets[num_segments] >= (1ull << 40)) return BITSORT_ERR_TOO_LARGE;
+  int rc = init_kernels();
+  if (rc != BITSORT_OK) return rc;
+  auto* p = new struct bitsort_batch_plan();
+  p->segments = num_segments;
+  p->max_keys = offsets[num_segments];
+  p->tuning = batch_tuning();
+  p->ws_bytes = batch_workspace_bytes(num_segments, p->tuning);
+  (void)hipGetDevice(&p->device);
+  if (hipMalloc(&p->ws, p->ws_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete p;
+    return BITSORT_ERR_NO_MEMORY;
+  }
+  *plan = p;
+  return BITSORT_OK;
+}
+
+int bitsort_batch_run(const bitsort_batch_plan_t* plan, const uint32_t* keys, const uint64_t* offsets,
+                      const uint8_t* range_bits, uint32_t* out, bitsort_stream_t stream) {
+  if (plan == nullptr) return BITSORT_ERR_INVALID_ARG;
+  int rc = check_batch_args(keys, offsets, plan->segments, range_bits, out, plan->max_keys);
+  if (rc != BITSORT_OK) return rc;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) return BITSORT_ERR_INVALID_ARG;
+  return run_batch(keys, offsets, plan->segments, range_bits, out, plan->max_keys, plan->ws,
+                   static_cast<hipStream_t>(stream), plan->tuning);
+}
+
+int bitsort_batch_plan_status(const bitsort_batch_plan_t* plan, bitsort_stream_t stream, bitsort_status_t* status,
+                              uint32_t count) {
+  if (plan == nullptr || status == nullptr || count > plan->segments) return BITSORT_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return BITSORT_ERR_HIP;
+  if (count == 0) return BITSORT_OK;
+  if (hipMemcpy(status, static_cast<const char*>(plan->ws) + kHeaderBytes, sizeof(SegStatus) * count,
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return BITSORT_ERR_HIP;
+  return BITSORT_OK;
+}
+
+int bitsort_batch_plan_destroy(bitsort_batch_plan_t* plan) {
+  if (plan == nullptr) return BITSORT_OK;
+  const int rc = (plan->ws != nullptr && hipFree(plan->ws) != hipSuccess) ? BITSORT_ERR_HIP : BITSORT_OK;
+  delete plan;
+  return rc;
 }
 
 // ---- graphs -------------------------------------------------------------------

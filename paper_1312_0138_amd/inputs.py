@@ -100,6 +100,23 @@ def distinct_uniform(n: int, bits: int, seed: int, chunk: int = 1 << 22) -> np.n
     return out
 
 
+def distinct_uniform_u64(n: int, bits: int, seed: int, chunk: int = 1 << 22) -> np.ndarray:
+    """n distinct uint64 keys in [0, 2^bits), bits <= 64, pseudo-random order:
+    the same Feistel network on wider halves (each at most 32 bits)."""
+    if not 0 <= bits <= 64:
+        raise ValueError("bits must be in [0, 64]")
+    if n > (1 << bits):
+        raise ValueError("n exceeds the key range")
+    out = np.zeros(n, dtype=np.uint64)
+    if bits == 0:
+        return out
+    rk = feistel_round_keys(seed)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        out[lo:hi] = _feistel(np.arange(lo, hi, dtype=np.uint64), bits, rk)
+    return out
+
+
 def dense_permutation(bits: int, seed: int) -> np.ndarray:
     """Every key of [0, 2^bits) once, in pseudo-random order."""
     return distinct_uniform(1 << bits, bits, seed)

@@ -49,3 +49,18 @@ def test_sizes_ranges_and_arrivals():
     t = inputs.poisson_arrivals(10_000, 1000.0, 3)
     assert np.all(np.diff(t) > 0)
     assert abs(t[-1] - 10.0) < 0.5
+
+
+@pytest.mark.parametrize("bits", [1, 9, 16])
+def test_distinct_uniform_u64_is_a_bijection_on_small_ranges(bits):
+    k = inputs.distinct_uniform_u64(1 << bits, bits, 11)
+    assert k.dtype == np.uint64
+    assert np.array_equal(np.sort(k), np.arange(1 << bits, dtype=np.uint64))
+
+
+@pytest.mark.parametrize("bits", [33, 36, 48])
+def test_distinct_uniform_u64_wide_ranges(bits):
+    k = inputs.distinct_uniform_u64(60_000, bits, 12)
+    assert np.unique(k).size == 60_000 and int(k.max()) < (1 << bits)
+    hist = np.bincount((k >> np.uint64(bits - 3)).astype(np.int64), minlength=8)
+    assert hist.min() > 60_000 / 8 * 0.9

@@ -58,6 +58,26 @@ def test_host_argument_checks(lib):
         E.BITSORT_ERR_TOO_LARGE
     assert E.bitsort_batch_ptr_u32(kp.ctypes.data, nn.ctypes.data, rb.ctypes.data, op.ctypes.data, 0, 0) == \
         E.BITSORT_ERR_INVALID_ARG
+    # batch plans are checked on the host before anything touches the device
+    plan = ctypes.c_void_p()
+    off_bad = np.array([1, 5], dtype=np.uint64)
+    off_ok = np.array([0, 5], dtype=np.uint64)
+    rb2 = np.array([2], dtype=np.uint8)
+    rb25 = np.array([25], dtype=np.uint8)
+    rb8 = np.array([8], dtype=np.uint8)
+    lib_ = E.lib()
+    assert lib_.bitsort_batch_plan(off_bad.ctypes.data, rb8.ctypes.data, 1, ctypes.byref(plan)) == \
+        E.BITSORT_ERR_INVALID_ARG                                   # offsets[0] != 0
+    assert lib_.bitsort_batch_plan(off_ok.ctypes.data, rb25.ctypes.data, 1, ctypes.byref(plan)) == \
+        E.BITSORT_ERR_INVALID_ARG                                   # width above the batch limit
+    assert lib_.bitsort_batch_plan(off_ok.ctypes.data, rb2.ctypes.data, 1, ctypes.byref(plan)) == \
+        E.BITSORT_ERR_TOO_LARGE                                     # 5 keys below 2^2
+    assert lib_.bitsort_batch_plan(off_ok.ctypes.data, rb8.ctypes.data, 0, ctypes.byref(plan)) == \
+        E.BITSORT_ERR_INVALID_ARG
+    assert lib_.bitsort_batch_plan(off_ok.ctypes.data, rb8.ctypes.data, 1, None) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_batch_run(0, fake, fake, fake, fake + 4096, 0) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_set_workspace(fake + 8, 1 << 20, 0) == E.BITSORT_ERR_INVALID_ARG  # misaligned
+    assert E.bitsort_set_workspace(fake, 100, 0) == E.BITSORT_ERR_INVALID_ARG          # smaller than the header
     # 2^20 + 1 empty arrays of range 2^32 plan 4096 slices each: 2^32 + 4096
     # slices in all, past the launch limit; rejected on the host before any
     # device call (the slice total would wrap in 32 bits)
