@@ -1863,7 +1863,7 @@ int bitsort_tuning_load(const char* path, int* entries) {
     if (std::sscanf(line, "{\"device\": \"%127[^\"]\", \"kind\": \"plain\", \"range_bits\": %u, \"log2n\": %u, "
                           "\"slice_bits\": %u, \"tile_log2\": %u, \"emit_path\": %u, \"ms\": %f}",
                     dev, &rb, &l2, &sb, &tl, &ep, &ms) == 7) {
-      if (dk != dev || rb > 32 || sb < kMinSliceBits || sb > kMaxSliceBits || tl < 12 || tl > 15 || ep > 2) continue;
+      if (dk != dev || rb > 32 || sb < kMinSliceBits || sb > kMaxSliceBits || tl < 12 || tl > 15 || ep > 3) continue;
       g_plain_tuned[{rb, l2}] = PlainTuning{sb, tl, ep, ms};
       ++count;
     } else if (std::sscanf(line, "{\"device\": \"%127[^\"]\", \"kind\": \"batch\", \"block\": %u, \"slice_bits\": %u}",

@@ -451,9 +451,9 @@ def test_tuning_knobs_keep_results(o, sb, tl, path):
 
 
 @pytest.mark.parametrize("n,rb,path", [((1 << 24) + 12345, 28, 2), ((1 << 23) + 7, 30, 0), ((1 << 24) + 1, 26, 1)])
-def test_partition_several_tiles_per_workgroup(o, n, rb, path):
-    """2^15-key tiles: one persistent partition workgroup per CU takes several tiles
-    (more than 256 tiles here), the last one ragged."""
+def test_partition_large_tiles(o, n, rb, path):
+    """2^15-key tiles (1024 threads of 32 keys, one workgroup per tile): more
+    than 256 tiles here, the last one ragged."""
     import paper_1312_0138_amd as bs
     keys = inputs.distinct_uniform(n, rb, 107 + rb)
     want, _, _ = o.bitmap_sort(keys, rb)

@@ -147,11 +147,25 @@ def test_tuning_cache_plumbing(lib, tmp_path):
         f'{{"device": "other:1", "kind": "plain", "range_bits": 27, "log2n": 24, "slice_bits": 18, '
         f'"tile_log2": 13, "emit_path": 1, "ms": 0.1}}\n'
         f'{{"device": "{dev}", "kind": "plain", "range_bits": 27, "log2n": 23, "slice_bits": 99, '
-        f'"tile_log2": 13, "emit_path": 1, "ms": 0.1}}\n')
+        f'"tile_log2": 13, "emit_path": 1, "ms": 0.1}}\n'
+        # the word-summary emission (path 3) survives a save and a load
+        f'{{"device": "{dev}", "kind": "plain", "range_bits": 32, "log2n": 23, "slice_bits": 20, '
+        f'"tile_log2": 14, "emit_path": 3, "ms": 0.1}}\n'
+        f'{{"device": "{dev}", "kind": "plain", "range_bits": 31, "log2n": 23, "slice_bits": 20, '
+        f'"tile_log2": 14, "emit_path": 4, "ms": 0.1}}\n')
     rc, n = _lib.bitsort_tuning_load(str(path))
-    assert rc == 0 and n == 1
+    assert rc == 0 and n == 2
     rc, sb, tl, nb, ep = _lib.bitsort_plan_info(1 << 25, 27)
     assert (sb, tl, ep) == (17, 13, 1)
+    rc, sb4, tl4, nb4, ep4 = _lib.bitsort_plan_info(1 << 23, 32)
+    assert (sb4, tl4, ep4) == (20, 14, 3)
+    saved = tmp_path / "again.jsonl"
+    assert _lib.bitsort_tuning_save(str(saved)) == 0
+    assert '"emit_path": 3' in saved.read_text()
+    _lib.bitsort_tuning_clear()
+    rc, n = _lib.bitsort_tuning_load(str(saved))
+    assert rc == 0 and n >= 2
+    assert _lib.bitsort_plan_info(1 << 23, 32)[1:] == (20, 14, nb4, 3)
     rc, sb2, tl2, nb2, ep2 = _lib.bitsort_plan_info(1 << 24, 27)
     assert sb2 != 17 or tl2 != 13
     _lib.bitsort_tuning_clear()
