@@ -184,7 +184,7 @@ void make_plan(uint64_t n, uint32_t rb, Plan* p, const PlainTuning* force = null
     p->off_binfo = kHeaderBytes;
     p->off_table = align256(p->off_binfo + 24ull * p->nb);
     p->off_staging = align256(p->off_table + 4ull * p->nt * (p->nb + 1));
-    p->bytes = align256(p->off_staging + 4ull * p->nt * p->tile_keys);
+    p->bytes = align256(p->off_staging + 4ull * p->nt * p->tile_keys + kStagingPad);
     // Emit through an HBM bit-vector when it is small next to the keys
     // (R/8 <= 2n): the bit-vector round trip costs 2R/8 bytes, and in return
     // the emission runs at full occupancy instead of beside a 2^sb-bit slice.
@@ -389,7 +389,7 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
       const uint32_t grid = std::max(8u, cus & ~7u);
       auto kernel = p.short_units ? k_slice_seq<kSliceBlock, kSliceUnroll, 16> : k_slice_seq<kSliceBlock, kSliceUnroll, 64>;
       hipLaunchKernelGGL(kernel, dim3(grid), dim3(kSliceBlock), p.slice_lds, stream, staging, table, p.nt,
-                         p.tile_keys, p.sb, p.nb, out, info, 0u - p.bias, n, pending);
+                         p.tile_keys, p.sb, p.nb, out, info, 0u - p.bias, n, p.stage_cap, pending);
       rc = launch_status();
     } else {
     const uint32_t grid = 8u * ((p.nb + 7u) / 8u);
@@ -588,7 +588,7 @@ int make_multi_plan(const uint32_t* const* keys, const uint64_t* n, const uint8_
   p->off_table = o;
   o = align256(o + 4ull * p->table_words);
   p->off_staging = o;
-  o = align256(o + 4ull * p->tiles * tile_keys);
+  o = align256(o + 4ull * p->tiles * tile_keys + kStagingPad);
   p->off_bitvec = o;
   o = align256(o + 4ull * p->bitvec_words);
   p->off_chunk = o;

@@ -151,6 +151,14 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* scratch)
   return uniform(tot);
 }
 
+// A pointer known to address device memory, such as one read from a
+// descriptor in memory: the cast lets the compiler use global instead of flat
+// loads and stores through it (a flat access also waits on the LDS counter).
+template <typename T>
+__device__ __forceinline__ T* as_global(T* p) {
+  return (T*)((__attribute__((address_space(1))) T*)reinterpret_cast<uintptr_t>(p));
+}
+
 __device__ __forceinline__ uint32_t atomic_load_flags(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

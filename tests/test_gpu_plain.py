@@ -271,6 +271,76 @@ def test_sparse_slices_over_several_rounds_of_tiles(o):
     np.testing.assert_array_equal(got, want)
 
 
+def _emission_shape_keys(rb, seed):
+    """Keys laid out for the summary emission's branches.  A 2^20-bit slice has
+    32768 words; its wave v covers words [2048 v, 2048 v + 2048), lane l of it the
+    32 words of summary word 64 v + l.  The emission keeps a lane's first eight
+    nonzero words in registers and stages the wave's keys in a window of 440.
+    Every wave of every fifth slice (every thirteenth at 2^30) gets one of these shapes:
+    0: 0-4 nonzero words per lane, 1-3 keys each (registers, window);
+    1: 440 keys, lanes 0-61 with seven one-key words, lane 62 with six (window full);
+    2: 441 keys, lanes 0-62 with seven one-key words (one key over the window);
+    3: eight one-key words in every lane (512 keys, over the window);
+    4: eight full words in every lane (16384 keys);
+    5: nine one-key words in lane 5, one in every other lane (a lane past eight);
+    6: eight one-key words in lanes 0-54 (440 keys, every register in use)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    slices = 1 << (rb - 20)
+
+    def words_for(base, count, full=False, keys_each=None):
+        offs = np.sort(rng.choice(32, size=count, replace=False)).astype(np.uint64)
+        for w in base + offs:
+            if full:
+                bits = np.arange(32, dtype=np.uint64)
+            else:
+                k = keys_each if keys_each is not None else int(rng.integers(1, 4))
+                bits = rng.choice(32, size=k, replace=False).astype(np.uint64)
+            parts.append(w * np.uint64(32) + bits)
+
+    step = 5 if rb <= 28 else 13
+    for s in range(0, slices, step):
+        for v in range(16):
+            shape = (s // step + v) % 7
+            for lane in range(64):
+                base = np.uint64(s * 32768 + (v * 64 + lane) * 32)
+                if shape == 0:
+                    words_for(base, int(rng.integers(0, 5)))
+                elif shape == 1:
+                    words_for(base, 7 if lane < 62 else (6 if lane == 62 else 0), keys_each=1)
+                elif shape == 2:
+                    words_for(base, 7 if lane < 63 else 0, keys_each=1)
+                elif shape == 3:
+                    words_for(base, 8, keys_each=1)
+                elif shape == 4:
+                    words_for(base, 8, full=True)
+                elif shape == 5:
+                    words_for(base, 9 if lane == 5 else 1, keys_each=1)
+                else:
+                    words_for(base, 8 if lane < 55 else 0, keys_each=1)
+    keys = np.concatenate(parts).astype(np.uint32)
+    return keys[rng.permutation(keys.size)]
+
+
+@pytest.mark.parametrize("rb", [28, 30])
+def test_sparse_emission_shapes(o, rb):
+    """The summary emission's register, window and fallback branches, each at its
+    edge, against the oracle: 2^28 runs one workgroup per slice (k_slice), 2^30
+    one workgroup walking many slices (k_slice_seq)."""
+    import paper_1312_0138_amd as bs
+    keys = _emission_shape_keys(rb, 40 + rb)
+    want, _, _ = o.bitmap_sort(keys, rb)
+    bs.set_tuning(20, 0, 3)
+    try:
+        plan = bs.plan_info(keys.size, rb)
+        assert plan["emit_path"] == "lds-sparse" and plan["buckets"] == 1 << (rb - 20), plan
+        got, st = _gpu_sort(keys, rb)
+    finally:
+        bs.set_tuning(0, 0, 0)
+    assert st.flags == 0 and st.count == keys.size
+    np.testing.assert_array_equal(got, want)
+
+
 def test_sparse_summary_duplicates_and_range(o):
     """Duplicates and keys beyond the range on the summary path: flags, count and the
     compacted output as the oracle gives them."""
@@ -433,6 +503,31 @@ def test_side_stream_and_workspace_variant(o):
     st2 = bs.workspace_status(ws)
     assert st2.flags == 0 and st2.count == keys.size
     np.testing.assert_array_equal(to_np(out2), want)
+
+
+# (range_bits, emit path): with 2^16-bit slices and 2^14-key tiles a tile's segment
+# holds about 2^(30 - rb) keys -- 512, 256, 128 -- so the waves' choice between
+# 64-key units and 256-key units (16-byte loads) falls on both sides.
+@pytest.mark.parametrize("rb", [21, 22, 23])
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("extra", [0, 3])
+def test_long_gather_units(o, rb, path, extra):
+    """The slice kernel's 256-key gather units around their switch point: full tiles
+    (the last slice's last segment ends where the staging area ends), or a last
+    tile of three keys."""
+    import paper_1312_0138_amd as bs
+    n = 37 * (1 << 14) + extra
+    keys = inputs.distinct_uniform(n, rb, 60 + rb)
+    want, _, _ = o.bitmap_sort(keys, rb)
+    bs.set_tuning(16, 14, path)
+    try:
+        plan = bs.plan_info(n, rb)
+        assert plan["slice_bits"] == 16 and plan["tile_log2"] == 14, plan
+        got, st = _gpu_sort(keys, rb)
+    finally:
+        bs.set_tuning(0, 0, 0)
+    assert st.flags == 0 and st.count == n
+    np.testing.assert_array_equal(got, want)
 
 
 @pytest.mark.parametrize("sb,tl,path", [(10, 12, 1), (14, 13, 1), (18, 14, 1), (20, 12, 1), (16, 14, 1),
