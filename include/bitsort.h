@@ -413,6 +413,16 @@ int bitsort_debug_bitmap_u32(const uint32_t *keys, uint64_t n, uint32_t range_bi
                              uint32_t *bitmap, bitsort_stream_t stream);
 int bitsort_debug_prefix_u32(const uint32_t *keys, uint64_t n, uint32_t range_bits,
                              uint64_t *prefix, bitsort_stream_t stream);
+/*
+ * - bitsort_debug_split_u32: after bitsort_u32_ws(keys, n, range_bits, ...,
+ *   workspace, ..., stream), synchronises `stream` and writes to host
+ *   *published how many slices that sort found heavy and published for
+ *   sharing among workgroups (bit-vector route; the first 64 are shared, the
+ *   rest stay whole); 0 when the plan for (n, range_bits) does not share
+ *   slices.  Reads 4 bytes of the workspace; changes nothing.
+ */
+int bitsort_debug_split_u32(const void *workspace, uint64_t n, uint32_t range_bits, uint32_t *published,
+                            bitsort_stream_t stream);
 
 /*
  * Tuning knobs for the plain path (0 = library default).
@@ -423,6 +433,13 @@ int bitsort_debug_prefix_u32(const uint32_t *keys, uint64_t n, uint32_t range_bi
  *               occupancy (k_slice + k_emit, needs slice_bits >= 15);
  *               3: emit from LDS through a summary bit per word, reading only
  *               nonzero words (needs slice_bits = 20);
+ *               4: path 2, and a slice holding more than four times the mean
+ *               keys (at least 2^16) is cut into up to 4 chunks of tiles that
+ *               workgroups done with their own slices mark into partial
+ *               slices and OR together; for skewed keys.  The workspace
+ *               grows by 256 partial slices (2^(slice_bits-3) bytes each:
+ *               32 MiB at 2^20-bit slices), which bitsort_workspace_bytes
+ *               includes;
  *               0: choose by size (the HBM bit-vector when R/8 <= 2n, the
  *               summary when n <= R/32 and the slice has 2^20 bits).
  * Affects calls made afterwards in this process.
@@ -431,7 +448,8 @@ int bitsort_set_tuning(uint32_t slice_bits, uint32_t tile_log2, uint32_t emit_pa
 
 /* The slice_bits, tile_log2 (0 for the single-workgroup path), number of
  * slices and emit path (0 single workgroup, 1 LDS, 2 HBM bit-vector, 3 LDS
- * through the word summary) that the plain path would use for (n, range_bits). */
+ * through the word summary, 4 HBM bit-vector with heavy slices shared) that
+ * the plain path would use for (n, range_bits). */
 int bitsort_plan_info(uint64_t n, uint32_t range_bits, uint32_t *slice_bits, uint32_t *tile_log2,
                       uint32_t *buckets, uint32_t *emit_path);
 

@@ -14,7 +14,7 @@ from ._lib import (BitsortError, STATUS_BAD_SEGMENT, STATUS_DUPLICATE,
 
 __all__ = [
     "sort", "status", "sort_batch", "batch_status", "generate", "debug_bitmap",
-    "debug_prefix", "workspace_bytes", "sort_ws", "workspace_status", "set_tuning",
+    "debug_prefix", "debug_split", "workspace_bytes", "sort_ws", "workspace_status", "set_tuning",
     "plan_info", "BitsortError", "Status", "STATUS_OUT_OF_RANGE", "STATUS_DUPLICATE",
     "STATUS_BAD_SEGMENT", "Graph", "autotune", "autotune_batch", "tuning_save", "tuning_load",
     "tuning_clear", "radix_sort", "radix_workspace_bytes", "radix_sort_ws", "STATUS_TIMEOUT", "sort_signed", "radix_sort_signed", "sort_multiset", "radix_sort_u64",
@@ -371,6 +371,14 @@ def debug_bitmap(keys, range_bits: int, stream=None):
     return bm
 
 
+def debug_split(workspace, n: int, range_bits: int, stream=None) -> int:
+    """How many slices the last ``sort_ws`` with this workspace found heavy
+    and published for sharing (0 when the plan does not share slices)."""
+    rc, published = _lib.bitsort_debug_split_u32(workspace.data_ptr(), n, range_bits, _stream(stream))
+    _lib.check(rc, "bitsort_debug_split_u32")
+    return published
+
+
 def debug_prefix(keys, range_bits: int, stream=None):
     """The scan step's exclusive per-word prefix of set bits (int64 words)."""
     torch = _torch()
@@ -386,7 +394,7 @@ def set_tuning(slice_bits: int = 0, tile_log2: int = 0, emit_path: int = 0) -> N
     _lib.check(_lib.bitsort_set_tuning(slice_bits, tile_log2, emit_path), "bitsort_set_tuning")
 
 
-EMIT_PATHS = {0: "single-workgroup", 1: "lds", 2: "hbm-bitvector", 3: "lds-sparse"}
+EMIT_PATHS = {0: "single-workgroup", 1: "lds", 2: "hbm-bitvector", 3: "lds-sparse", 4: "hbm-bitvector-shared"}
 
 
 def plan_info(n: int, range_bits: int):

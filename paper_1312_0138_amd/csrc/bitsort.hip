@@ -104,7 +104,9 @@ struct Plan {
   bool sparse = false;      // k_slice keeps a summary bit per word and emits only nonzero words
   bool short_units = false; // segments of a few keys: k_slice gathers 16-key units, four per load
   uint64_t n_chunks = 0;
+  bool split = false;       // bit-vector route: heavy slices are shared out (k_slice_split)
   size_t off_binfo = 0, off_table = 0, off_staging = 0, off_bitvec = 0, off_chunk = 0, bytes = 0;
+  size_t off_split_ctl = 0, off_partials = 0;
   uint32_t stage_cap = 0;
   size_t slice_lds = 0;
   uint32_t bias = 0;  // signed keys: added on load, subtracted on output (mod 2^32)
@@ -191,12 +193,22 @@ void make_plan(uint64_t n, uint32_t rb, Plan* p, const PlainTuning* force = null
     uint32_t path = force ? 0u : g_tune_path.load();
     if (path == 0) path = tuned.emit_path;
     const uint64_t bv_bytes = (1ull << rb) / 8u;
-    if ((1u << (sb - 5)) >= kChunkWords && (path == 2 || (path == 0 && bv_bytes <= 2 * n))) {
+    if ((1u << (sb - 5)) >= kChunkWords && (path == 2 || path == 4 || (path == 0 && bv_bytes <= 2 * n))) {
       p->via_bitvec = true;
       p->n_chunks = (1ull << (rb - 5)) / kChunkWords;
       p->off_bitvec = p->bytes;
       p->off_chunk = align256(p->off_bitvec + bv_bytes);
       p->bytes = align256(p->off_chunk + 8ull * p->n_chunks);
+      // Path 4 (asked for: it pays on skewed keys, where a few slices hold
+      // several times the mean, and costs a table read on even ones):
+      // heavy slices are shared out.  Enough tiles to cut a heavy slice into
+      // chunks; its control words and kSplitMax * kSplitParts partial slices.
+      if (path == 4 && p->nt >= 2u * kSplitMinTiles && p->nb >= 2u) {
+        p->split = true;
+        p->off_split_ctl = p->bytes;
+        p->off_partials = align256(p->off_split_ctl + 4ull * kSplitCtlWords);
+        p->bytes = align256(p->off_partials + 4ull * kSplitMax * kSplitParts * (1ull << (sb - 5)));
+      }
     }
     // About one key per word or fewer: the slice kernel also keeps a summary
     // bit per word and its emission reads only nonzero words.  Needs the full
@@ -247,6 +259,8 @@ int init_kernels() {
     set_lds_attr(k_slice<kSliceBlock, kSliceUnroll, true, 64>, kLdsBytes);
     set_lds_attr(k_slice<kSliceBlock, kSliceUnroll, false, 16>, kLdsBytes);
     set_lds_attr(k_slice<kSliceBlock, kSliceUnroll, true, 16>, kLdsBytes);
+    set_lds_attr(k_slice_split<kSliceBlock, kSliceUnroll, 16>, kLdsBytes);
+    set_lds_attr(k_slice_split<kSliceBlock, kSliceUnroll, 64>, kLdsBytes);
     set_lds_attr(k_slice_seq<kSliceBlock, kSliceUnroll, 16>, kLdsBytes);
     set_lds_attr(k_slice_seq<kSliceBlock, kSliceUnroll, 64>, kLdsBytes);
     set_lds_attr(k_direct<kDirectBlock>, kLdsBytes);
@@ -313,7 +327,7 @@ struct LaunchTimer {
 // Enqueue the plain path.  mode != kEmit writes the debug dumps instead.
 // Partition launch shared by the bitmap and the counting path.
 int launch_partition(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* staging, uint32_t* table,
-                     hipStream_t stream) {
+                     hipStream_t stream, uint32_t* split_ctl = nullptr, Status* status = nullptr) {
   const uint64_t range = 1ull << p.rb;
   const int vec_ok = (reinterpret_cast<uintptr_t>(keys) % 16u) == 0 ? 1 : 0;
   const size_t part_lds = 4ull * (32 + round_up4(p.nb) + p.tile_keys);
@@ -321,19 +335,19 @@ int launch_partition(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* 
   switch (p.tile_log2) {
     case 12:  // 4096-key tiles: 1024 threads of 4 keys, so that a small input's few tiles still fill the CUs
       hipLaunchKernelGGL((k_partition<1024, 4>), dim3(p.nt), dim3(1024), part_lds, stream, keys, n, range, p.sb,
-                         p.nb, staging, table, vec_ok, p.bias);
+                         p.nb, staging, table, vec_ok, p.bias, split_ctl, status);
       break;
     case 13:
       hipLaunchKernelGGL((k_partition<512, 16>), dim3(p.nt), dim3(512), part_lds, stream, keys, n, range, p.sb, p.nb,
-                         staging, table, vec_ok, p.bias);
+                         staging, table, vec_ok, p.bias, split_ctl, status);
       break;
     case 14:
       hipLaunchKernelGGL((k_partition<1024, 16>), dim3(p.nt), dim3(1024), part_lds, stream, keys, n, range, p.sb,
-                         p.nb, staging, table, vec_ok, p.bias);
+                         p.nb, staging, table, vec_ok, p.bias, split_ctl, status);
       break;
     default:
       hipLaunchKernelGGL((k_partition<1024, 32>), dim3(p.nt), dim3(1024), part_lds, stream, keys, n, range, p.sb,
-                         p.nb, staging, table, vec_ok, p.bias);
+                         p.nb, staging, table, vec_ok, p.bias, split_ctl, status);
       break;
   }
   return launch_status();
@@ -373,7 +387,9 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
   uint32_t* table = reinterpret_cast<uint32_t*>(base + p.off_table);
   uint32_t* staging = reinterpret_cast<uint32_t*>(base + p.off_staging);
   uint64_t* info = reinterpret_cast<uint64_t*>(base + p.off_binfo);
-  rc = launch_partition(p, keys, n, staging, table, stream);
+  const bool split = p.split && mode == kEmit;
+  uint32_t* split_ctl = split ? reinterpret_cast<uint32_t*>(base + p.off_split_ctl) : nullptr;
+  rc = launch_partition(p, keys, n, staging, table, stream, split_ctl, status);
   if (rc != BITSORT_OK) return rc;
   uint32_t* bitvec = reinterpret_cast<uint32_t*>(base + p.off_bitvec);
   uint64_t* chunk_base = reinterpret_cast<uint64_t*>(base + p.off_chunk);
@@ -383,7 +399,18 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
   {
     LaunchTimer timer(kKSlice, stream);
     const uint32_t cus = device_cus();
-    if (p.sparse && mode == kEmit && p.nb > cus) {
+    if (split) {
+      // bit-vector route: slices of more than four times the mean (and 2^16
+      // keys or more) are shared out among the workgroups that finish early
+      const uint32_t grid = 8u * ((p.nb + 7u) / 8u);
+      const uint64_t heavy = std::max<uint64_t>(4 * ((n + p.nb - 1) / p.nb), 1ull << 16);
+      auto kernel = p.short_units ? k_slice_split<kSliceBlock, kSliceUnroll, 16>
+                                  : k_slice_split<kSliceBlock, kSliceUnroll, 64>;
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(kSliceBlock), p.slice_lds, stream, staging, table, p.nt,
+                         p.tile_keys, p.sb, p.nb, info, bitvec, chunk_base, split_ctl,
+                         reinterpret_cast<uint32_t*>(base + p.off_partials), heavy, n, out, pending, status);
+      rc = launch_status();
+    } else if (p.sparse && mode == kEmit && p.nb > cus) {
       // many sparse slices: one workgroup per CU (a multiple of 8), each
       // taking every (grid/8)-th slice of its XCD's run
       const uint32_t grid = std::max(8u, cus & ~7u);
@@ -414,7 +441,8 @@ int run_plain(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
   }
   if (defer) return BITSORT_OK;
   LaunchTimer timer(kKFinish, stream);
-  hipLaunchKernelGGL((k_finish<kSliceBlock>), dim3(1), dim3(kSliceBlock), 0, stream, n, p.nb, info, status, out);
+  hipLaunchKernelGGL((k_finish<kSliceBlock>), dim3(1), dim3(kSliceBlock), 0, stream, n, p.nb, info, status, out,
+                     split ? BITSORT_STATUS_TIMEOUT : 0u);
   return launch_status();
 }
 
@@ -459,7 +487,8 @@ int run_count(const Plan& p, const uint32_t* keys, uint64_t n, uint32_t* out, vo
     if ((rc = launch_status()) != BITSORT_OK) return rc;
   }
   LaunchTimer timer(kKFinish, stream);
-  hipLaunchKernelGGL((k_finish<kSliceBlock>), dim3(1), dim3(kSliceBlock), 0, stream, n, p.nb, info, status, out);
+  hipLaunchKernelGGL((k_finish<kSliceBlock>), dim3(1), dim3(kSliceBlock), 0, stream, n, p.nb, info, status, out,
+                     0u);
   return launch_status();
 }
 
@@ -915,7 +944,7 @@ int read_plain_status(void* ws, hipStream_t stream, bitsort_status_t* st) {
       return BITSORT_ERR_HIP;
     if (d.nb == 0 || d.info == nullptr) return BITSORT_ERR_INVALID_ARG;
     hipLaunchKernelGGL((k_finish<kSliceBlock>), dim3(1), dim3(kSliceBlock), 0, stream, d.n, d.nb, d.info,
-                       static_cast<Status*>(ws), d.out);
+                       static_cast<Status*>(ws), d.out, d.keep);
     if (launch_status() != BITSORT_OK || hipStreamSynchronize(stream) != hipSuccess) return BITSORT_ERR_HIP;
     if (hipMemcpy(&s, ws, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess) return BITSORT_ERR_HIP;
   }
@@ -1863,7 +1892,7 @@ int bitsort_tuning_load(const char* path, int* entries) {
     if (std::sscanf(line, "{\"device\": \"%127[^\"]\", \"kind\": \"plain\", \"range_bits\": %u, \"log2n\": %u, "
                           "\"slice_bits\": %u, \"tile_log2\": %u, \"emit_path\": %u, \"ms\": %f}",
                     dev, &rb, &l2, &sb, &tl, &ep, &ms) == 7) {
-      if (dk != dev || rb > 32 || sb < kMinSliceBits || sb > kMaxSliceBits || tl < 12 || tl > 15 || ep > 3) continue;
+      if (dk != dev || rb > 32 || sb < kMinSliceBits || sb > kMaxSliceBits || tl < 12 || tl > 15 || ep > 4) continue;
       g_plain_tuned[{rb, l2}] = PlainTuning{sb, tl, ep, ms};
       ++count;
     } else if (std::sscanf(line, "{\"device\": \"%127[^\"]\", \"kind\": \"batch\", \"block\": %u, \"slice_bits\": %u}",
@@ -1994,11 +2023,24 @@ int bitsort_profile_read(bitsort_profile_entry_t* entries, int max_entries, int*
 int bitsort_set_tuning(uint32_t slice_bits, uint32_t tile_log2, uint32_t emit_path) {
   if (slice_bits != 0 && (slice_bits < kMinSliceBits || slice_bits > kMaxSliceBits)) return BITSORT_ERR_INVALID_ARG;
   if (tile_log2 != 0 && (tile_log2 < 12 || tile_log2 > 15)) return BITSORT_ERR_INVALID_ARG;
-  if (emit_path > 3) return BITSORT_ERR_INVALID_ARG;
+  if (emit_path > 4) return BITSORT_ERR_INVALID_ARG;
   g_tune_sb.store(slice_bits);
   g_tune_tile.store(tile_log2);
   g_tune_path.store(emit_path);
   return BITSORT_OK;
+}
+
+int bitsort_debug_split_u32(const void* workspace, uint64_t n, uint32_t range_bits, uint32_t* published,
+                            bitsort_stream_t stream) {
+  if (workspace == nullptr || published == nullptr || range_bits > 32) return BITSORT_ERR_INVALID_ARG;
+  *published = 0;
+  Plan p;
+  make_plan(n, range_bits, &p);
+  if (p.direct || !p.split) return BITSORT_OK;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return BITSORT_ERR_HIP;
+  const char* ctl = static_cast<const char*>(workspace) + p.off_split_ctl;
+  return hipMemcpy(published, ctl, sizeof(uint32_t), hipMemcpyDeviceToHost) == hipSuccess ? BITSORT_OK
+                                                                                        : BITSORT_ERR_HIP;
 }
 
 int bitsort_plan_info(uint64_t n, uint32_t range_bits, uint32_t* slice_bits, uint32_t* tile_log2,
@@ -2011,7 +2053,7 @@ int bitsort_plan_info(uint64_t n, uint32_t range_bits, uint32_t* slice_bits, uin
   *slice_bits = p.sb;
   *tile_log2 = p.direct ? 0 : p.tile_log2;
   *buckets = p.nb;
-  *emit_path = p.direct ? 0u : (p.via_bitvec ? 2u : (p.sparse ? 3u : 1u));
+  *emit_path = p.direct ? 0u : (p.split ? 4u : (p.via_bitvec ? 2u : (p.sparse ? 3u : 1u)));
   return BITSORT_OK;
 }
 

@@ -34,7 +34,7 @@ struct PendingFinish {
   const uint64_t* info;   // per-slice (base, ones, keys) triples
   uint32_t* out;          // the sorted output
   uint32_t nb;            // slices
-  uint32_t _pad;
+  uint32_t keep;          // status flags raised by the slice kernel that the finish step keeps
 };
 
 __device__ __forceinline__ uint32_t lane_id() {

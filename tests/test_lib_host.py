@@ -38,9 +38,12 @@ def test_host_argument_checks(lib):
     assert E.bitsort_u32(fake, 100, 10, fake + 4, 0) == E.BITSORT_ERR_INVALID_ARG  # partial overlap
     assert E.bitsort_workspace_bytes(10, 3) == 0
     assert E.bitsort_workspace_bytes(10, 33) == 0
+    assert E.bitsort_debug_split_u32(0, 10, 24, 0)[0] == E.BITSORT_ERR_INVALID_ARG      # no workspace
+    assert E.bitsort_debug_split_u32(fake, 10, 33, 0)[0] == E.BITSORT_ERR_INVALID_ARG   # range_bits > 32
+    assert E.bitsort_debug_split_u32(fake, 1000, 24, 0) == (E.BITSORT_OK, 0)           # a plan that shares nothing
     assert E.bitsort_set_tuning(9, 0, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_set_tuning(0, 16, 0) == E.BITSORT_ERR_INVALID_ARG
-    assert E.bitsort_set_tuning(0, 0, 4) == E.BITSORT_ERR_INVALID_ARG
+    assert E.bitsort_set_tuning(0, 0, 5) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_batch_u32(fake, fake, 0, fake, fake, 0, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_generate_u32(fake, 10, 1, 3, 0, 0) == E.BITSORT_ERR_TOO_LARGE
     assert E.bitsort_radix_u32(fake, 10, 33, fake + 4096, 0) == E.BITSORT_ERR_INVALID_ARG
@@ -152,7 +155,7 @@ def test_tuning_cache_plumbing(lib, tmp_path):
         f'{{"device": "{dev}", "kind": "plain", "range_bits": 32, "log2n": 23, "slice_bits": 20, '
         f'"tile_log2": 14, "emit_path": 3, "ms": 0.1}}\n'
         f'{{"device": "{dev}", "kind": "plain", "range_bits": 31, "log2n": 23, "slice_bits": 20, '
-        f'"tile_log2": 14, "emit_path": 4, "ms": 0.1}}\n')
+        f'"tile_log2": 14, "emit_path": 5, "ms": 0.1}}\n')
     rc, n = _lib.bitsort_tuning_load(str(path))
     assert rc == 0 and n == 2
     rc, sb, tl, nb, ep = _lib.bitsort_plan_info(1 << 25, 27)
