@@ -27,6 +27,8 @@ Workloads:
   radix-sparse    the plain-sparse input through the LSD radix sort
   radix-u64       2^25 uint64 keys through the 64-bit radix sort (8 passes)
   radix-pairs     2^26 uint32 keys with uint32 values (key-value radix sort)
+  bitmap-pairs    2^26 distinct keys in [0, 2^28), each with a uint32 value,
+                  through the bitmap sort of key-value records
   signed-uniform  2^26 distinct int32 keys in [-2^27, 2^27), signed bitmap sort
   count-uniform   2^26 keys in [0, 2^24) with repeats, counting (multiset) sort
   batch           4096 arrays, sizes log-uniform in [256, 2^20], range the
@@ -68,6 +70,9 @@ PLAIN = {
                       desc="2^25 uint64 keys uniform in [0, 2^64) with repeats; LSD radix, 8 passes"),
     "radix-pairs": dict(n=1 << 26, rb=32, cfg=8, sorter="pairs",
                         desc="2^26 uint32 keys uniform in [0, 2^32) with repeats, each with a uint32 value; 4 passes"),
+    "bitmap-pairs": dict(n=1 << 26, rb=28, cfg=2, sorter="bitmap_pairs",
+                         desc="2^26 distinct uint32 keys uniform in [0, 2^28), each with a uint32 value; bitmap sort "
+                              "of the records"),
     "signed-uniform": dict(n=1 << 26, rb=28, cfg=9, sorter="signed",
                            desc="2^26 distinct int32 keys uniform in [-2^27, 2^27); bitmap sort with the signed shift"),
     "count-uniform": dict(n=1 << 26, rb=24, cfg=10, sorter="count",
@@ -80,6 +85,7 @@ KERNEL_SOURCES = {
     "batch": ["bitsort_device.h", "plain_kernels.inc", "batch_kernels.inc"],
     "radix": ["bitsort_device.h", "radix_kernels.inc"],
     "count": ["bitsort_device.h", "plain_kernels.inc", "count_kernels.inc"],
+    "pairs": ["bitsort_device.h", "plain_kernels.inc", "pairs_kernels.inc"],
 }
 
 
@@ -129,6 +135,19 @@ def radix_algorithmic_bytes(n: int, key_bits: int, elem_bytes: int = 4) -> dict:
     return {"k_radix_pass": 2 * e * n, "k_radix_hist": 0, "k_radix_scan": 0, "path": passes * 2 * e * n}
 
 
+def pairs_algorithmic_bytes(n: int, rb: int, emit_path: str) -> dict:
+    """The bitmap sort of key-value records: keys and values in (8n), one pass
+    over the bit-vector (R/8), keys and values out (8n).  Records route: the
+    partition reads the records, the slice step makes the bit-vector pass and
+    writes them.  Table route: the plain sort's kernels as for the keys alone,
+    the scatter credited with the values in and the gather with the values out."""
+    r8 = (1 << rb) // 8
+    ab = algorithmic_bytes(n, rb, emit_path)
+    ab.update({"k_partition_kv": 8 * n, "k_slice_kv": r8 + 8 * n, "k_pairs_finish": 0,
+               "k_pairs_scatter": 4 * n, "k_pairs_gather": 4 * n, "path": ab["path"] + 8 * n})
+    return ab
+
+
 def count_algorithmic_bytes(n: int, rb: int) -> dict:
     """The counting sort credited like the bitmap: keys in, one pass over the
     key range's presence (R/8), keys out; the counters themselves stay in LDS."""
@@ -155,11 +174,14 @@ def read_traffic(kernel: str, workload: str, digest: str):
         return None
 
 
+PAIRS = ("pairs", "bitmap_pairs")
+
+
 def cpu_baseline(host, sorter: str, rb: int, budget_s: float = 12.0, max_reps: int = 5):
     """The oracle, single-threaded, timed on the host: (Gkeys/s, reps, median s, out)."""
     import oracle
     fn = oracle_fn(oracle.default(), sorter, rb)
-    n = host[0].size if sorter == "pairs" else host.size
+    n = host[0].size if sorter in PAIRS else host.size
     times, out = [], None
     t_start = time.perf_counter()
     for _ in range(max_reps):
@@ -197,6 +219,8 @@ def make_plain_inputs(bs, torch, spec, workload, pool):
         bs.generate(n, rb, inputs.config_seed(cfg, rep), out=t)
         if sorter == "signed":
             t -= 1 << (rb - 1)  # onto [-2^(rb-1), 2^(rb-1))
+        if sorter == "bitmap_pairs":  # value of record i: i + rep
+            t = (t, torch.arange(rep, rep + n, dtype=torch.int32, device="cuda"))
         bufs.append(t)
     return bufs, n
 
@@ -219,6 +243,8 @@ def host_input(spec, workload, n, rep=0):
     if workload == "plain-clustered":
         return inputs.clustered(1 << 26, rb, inputs.config_seed(cfg, 1))
     keys = inputs.distinct_uniform(n, rb, inputs.config_seed(cfg, rep))
+    if sorter == "bitmap_pairs":
+        return keys, np.arange(rep, rep + n, dtype=np.uint32)
     if sorter == "signed":
         return (keys.astype(np.int64) - (1 << (rb - 1))).astype(np.int32)
     return keys
@@ -234,6 +260,7 @@ def sort_fn(bs, sorter):
         "radix": lambda x, rb, out: bs.radix_sort(x, rb, out),
         "radix64": lambda x, rb, out: bs.radix_sort_u64(x, rb, out),
         "pairs": lambda x, rb, out: bs.radix_sort_pairs(x[0], x[1], rb, out[0], out[1]),
+        "bitmap_pairs": lambda x, rb, out: bs.sort_pairs(x[0], x[1], rb, out[0], out[1]),
     }[sorter]
 
 
@@ -253,6 +280,7 @@ def oracle_fn(o, sorter, rb):
         "radix": lambda keys: o.bitwise_sort1(keys, rb),
         "radix64": lambda keys: o.bitwise_sort1_u64(keys, rb),
         "pairs": lambda kv: o.bitwise_sort1_pairs(kv[0], kv[1], rb),
+        "bitmap_pairs": lambda kv: o.bitwise_sort1_pairs(kv[0], kv[1], rb),
     }[sorter]
 
 
@@ -264,6 +292,7 @@ ORACLE_KIND = {
     "radix": "single-threaded C oracle (Algorithm 1, one-bit passes)",
     "radix64": "single-threaded C oracle (Algorithm 1 for uint64, 64 one-bit passes)",
     "pairs": "single-threaded C oracle (Algorithm 1 on key-value records)",
+    "bitmap_pairs": "single-threaded C oracle (Algorithm 1 on key-value records, range_bits passes)",
 }
 
 
@@ -286,13 +315,13 @@ def bench_plain(args, workload):
     sort = sort_fn(bs, sorter)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    elem = {"radix64": 8, "pairs": 8}.get(sorter, 4)
+    elem = {"radix64": 8, "pairs": 8, "bitmap_pairs": 8}.get(sorter, 4)
     pool = args.pool
     if pool == 0:
         per = elem * (spec["n"] or (1 << 26))
         pool = max(2, min(128, -(-2 * MALL_BYTES // per)))
     bufs, n = make_plain_inputs(bs, torch, spec, workload, pool)
-    if sorter == "pairs":
+    if sorter in PAIRS:
         out = (torch.empty(n, dtype=torch.int32, device="cuda"), torch.empty(n, dtype=torch.int32, device="cuda"))
     else:
         out = torch.empty_like(bufs[0])
@@ -358,6 +387,8 @@ def bench_plain(args, workload):
         ab = radix_algorithmic_bytes(n, rb, elem)
     elif sorter == "count":
         ab = count_algorithmic_bytes(n, rb)
+    elif sorter == "bitmap_pairs":
+        ab = pairs_algorithmic_bytes(n, rb, bs.plan_info(n, rb)["emit_path"])
     elif sorter == "atomic":
         ab = atomic_algorithmic_bytes(n, rb)
     else:
@@ -365,7 +396,7 @@ def bench_plain(args, workload):
     kernels = {k: {"launches": int(l), "avg_us": round(1e3 * ms / max(l, 1), 3)} for k, (l, ms) in prof.items()}
     dom = max(prof, key=lambda k: prof[k][1])
     dom_avg_s = prof[dom][1] / prof[dom][0] / 1e3
-    digest = source_digest("radix" if radix else ("count" if sorter == "count" else "plain"))
+    digest = source_digest("radix" if radix else {"count": "count", "bitmap_pairs": "pairs"}.get(sorter, "plain"))
     achieved = ab[dom] / dom_avg_s / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
@@ -387,7 +418,8 @@ def bench_plain(args, workload):
         "metric": METRIC, "value": round(value, 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": {"signed": "i32", "radix64": "u64", "pairs": "u32+u32"}.get(sorter, "u32"), "data": "synthetic",
+        "dtype": {"signed": "i32", "radix64": "u64", "pairs": "u32+u32", "bitmap_pairs": "u32+u32"}.get(sorter, "u32"),
+        "data": "synthetic",
         "config": config,
         "p50_ms": round(p50, 5), "p99_ms": round(p99, 5),
         "profiled_ms_per_step": round(sum(step_ms) / len(step_ms), 5),
@@ -402,7 +434,7 @@ def bench_plain(args, workload):
         host = host_input(spec, workload, n)
         gk, reps, med, want = cpu_baseline(host, sorter, rb)
         # the GPU result for the same input must equal the oracle's
-        if sorter == "pairs":
+        if sorter in PAIRS:
             dev = tuple(torch.from_numpy(h.view(np.int32)).cuda() for h in host)
             got_k, got_v = sort(dev, rb, (torch.empty_like(dev[0]), torch.empty_like(dev[1])))
             same = (np.array_equal(got_k.cpu().numpy().view(np.uint32), want[0])

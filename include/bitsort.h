@@ -186,13 +186,16 @@ int bitsort_get_status(bitsort_stream_t stream, bitsort_status_t *status);
 
 /*
  * Give the library a workspace for the calls on `stream` (bitsort_u32,
- * bitsort_i32, bitsort_count_u32 and the radix sorts), instead of the memory
+ * bitsort_i32, bitsort_pairs_u32, bitsort_count_u32 and the radix sorts),
+ * instead of the memory
  * it would allocate and keep for that stream.
  *   workspace  device pointer, 256-byte aligned, or NULL: the library
  *              allocates its own again on the next call that needs it.
  *   bytes      its size (at least 256); a later call whose workspace
- *              (bitsort_workspace_bytes, bitsort_radix_workspace_bytes) is
- *              larger returns BITSORT_ERR_NO_MEMORY and allocates nothing.
+ *              (bitsort_workspace_bytes, bitsort_radix_workspace_bytes;
+ *              for bitsort_pairs_u32 the first rounded up to 256 plus
+ *              4 * 2^range_bits) is larger returns BITSORT_ERR_NO_MEMORY
+ *              and allocates nothing.
  * The caller owns the memory, keeps it alive and leaves it alone while work
  * enqueued on `stream` may still use it; the library never frees it.  A
  * workspace the library had allocated for the stream is freed here (after
@@ -387,6 +390,27 @@ int bitsort_radix_u64(const uint64_t *keys, uint64_t n, uint32_t key_bits, uint6
  */
 int bitsort_radix_pairs_u32(const uint32_t *keys, const uint32_t *values, uint64_t n, uint32_t key_bits,
                             uint32_t *out_keys, uint32_t *out_values, bitsort_stream_t stream);
+
+/*
+ * Bitmap sort of (key, value) records: Section V's element type T taken as a
+ * record ordered by its key, sorted by the marking, counting and emission of
+ * bitsort_u32 (Table I, Examples 2-3, 6 and 1; Theorem 1: with distinct keys
+ * the ascending arrangement, values included, is unique).
+ *   out_keys      as bitsort_u32 writes them;
+ *   out_values[j] the value that came with out_keys[j].
+ * The values ride on a table of 2^range_bits words indexed by key, kept in
+ * the stream's workspace (plain workspace plus 4 * 2^range_bits bytes):
+ * values[i] goes to table[keys[i]] before the sort and out_values[j] =
+ * table[out_keys[j]] after it.  range_bits <= 30 (BITSORT_ERR_INVALID_ARG
+ * otherwise).  Status (bitsort_get_status) as for bitsort_u32; a repeated key
+ * keeps one of its values (which one is unspecified); entries past the
+ * status count are unspecified, as for the keys.  out_keys may equal keys and
+ * out_values may equal values; any other overlap among the four arrays, or a
+ * null array with n > 0, is BITSORT_ERR_INVALID_ARG.  Stream-ordered,
+ * allocation only when the workspace grows.
+ */
+int bitsort_pairs_u32(const uint32_t *keys, const uint32_t *values, uint64_t n, uint32_t range_bits,
+                      uint32_t *out_keys, uint32_t *out_values, bitsort_stream_t stream);
 
 /*
  * Device-side input generator (the synthetic workloads): out[i] = pi(first + i)

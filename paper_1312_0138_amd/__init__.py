@@ -18,7 +18,7 @@ __all__ = [
     "plan_info", "BitsortError", "Status", "STATUS_OUT_OF_RANGE", "STATUS_DUPLICATE",
     "STATUS_BAD_SEGMENT", "Graph", "autotune", "autotune_batch", "tuning_save", "tuning_load",
     "tuning_clear", "radix_sort", "radix_workspace_bytes", "radix_sort_ws", "STATUS_TIMEOUT", "sort_signed", "radix_sort_signed", "sort_multiset", "radix_sort_u64",
-    "radix_sort_pairs", "sort_many", "BatchPlan", "set_workspace", "sort_atomic", "sort_u64",
+    "radix_sort_pairs", "sort_many", "BatchPlan", "set_workspace", "sort_atomic", "sort_u64", "sort_pairs",
 ]
 
 
@@ -56,6 +56,27 @@ def sort(keys, range_bits: int, out=None, stream=None):
     _lib.check(_lib.bitsort_u32(keys.data_ptr(), keys.numel(), range_bits, out.data_ptr(), _stream(stream)),
                "bitsort_u32")
     return out
+
+
+def sort_pairs(keys, values, range_bits: int, out_keys=None, out_values=None, stream=None):
+    """Bitmap sort of (key, value) records with distinct keys below
+    2^range_bits (range_bits <= 30): returns (out_keys, out_values), the
+    values following their keys (bitsort_pairs_u32); status with status()."""
+    torch = _torch()
+    _check_u32(keys, "keys")
+    _check_u32(values, "values")
+    if values.numel() != keys.numel():
+        raise ValueError("values must have as many elements as keys")
+    out_keys = torch.empty_like(keys) if out_keys is None else out_keys
+    out_values = torch.empty_like(values) if out_values is None else out_values
+    _check_u32(out_keys, "out_keys")
+    _check_u32(out_values, "out_values")
+    if out_keys.numel() != keys.numel() or out_values.numel() != keys.numel():
+        raise ValueError("the outputs must have as many elements as keys")
+    _lib.check(_lib.bitsort_pairs_u32(keys.data_ptr(), values.data_ptr(), keys.numel(), range_bits,
+                                      out_keys.data_ptr(), out_values.data_ptr(), _stream(stream)),
+               "bitsort_pairs_u32")
+    return out_keys, out_values
 
 
 def sort_atomic(keys, range_bits: int, out=None, stream=None):

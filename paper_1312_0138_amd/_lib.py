@@ -81,6 +81,7 @@ _SIGS = {
     "bitsort_generate_u32": (_c.c_int, [_vp, _u64, _u64, _u32, _u64, _vp]),
     "bitsort_debug_bitmap_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
     "bitsort_debug_prefix_u32": (_c.c_int, [_vp, _u64, _u32, _vp, _vp]),
+    "bitsort_pairs_u32": (_c.c_int, [_vp, _vp, _u64, _u32, _vp, _vp, _vp]),
     "bitsort_debug_split_u32": (_c.c_int, [_vp, _u64, _u32, _c.POINTER(_u32), _vp]),
     "bitsort_set_tuning": (_c.c_int, [_u32, _u32, _u32]),
     "bitsort_plan_info": (_c.c_int, [_u64, _u32, _c.POINTER(_u32), _c.POINTER(_u32), _c.POINTER(_u32),
@@ -276,6 +277,11 @@ def bitsort_debug_bitmap_u32(keys: int, n: int, range_bits: int, bitmap: int, st
 
 def bitsort_debug_prefix_u32(keys: int, n: int, range_bits: int, prefix: int, stream: int) -> int:
     return lib().bitsort_debug_prefix_u32(keys, n, range_bits, prefix, stream)
+
+
+def bitsort_pairs_u32(keys: int, values: int, n: int, range_bits: int, out_keys: int, out_values: int,
+                      stream: int) -> int:
+    return lib().bitsort_pairs_u32(keys, values, n, range_bits, out_keys, out_values, stream)
 
 
 def bitsort_debug_split_u32(workspace: int, n: int, range_bits: int, stream: int):

@@ -95,6 +95,9 @@ namespace {
 #include "wide_kernels.inc"
 
 // ---------------------------------------------------------------------------
+#include "pairs_kernels.inc"
+
+// ---------------------------------------------------------------------------
 // Host side.
 
 struct Plan {
@@ -271,6 +274,11 @@ int init_kernels() {
     set_lds_attr(k_batch_run<256>, kLdsBytes);
     set_lds_attr(k_batch_run<512>, kLdsBytes);
     set_lds_attr(k_batch_run<1024>, kLdsBytes);
+    set_lds_attr(k_partition_kv<1024, 4>, kLdsBytes);
+    set_lds_attr(k_partition_kv<1024, 16>, kLdsBytes);
+    set_lds_attr(k_partition_kv<1024, 32>, kLdsBytes);
+    set_lds_attr(k_slice_kv<kSliceBlock, kSliceUnroll, 16>, kLdsBytes);
+    set_lds_attr(k_slice_kv<kSliceBlock, kSliceUnroll, 64>, kLdsBytes);
   });
   return g_attr_err == hipSuccess ? BITSORT_OK : BITSORT_ERR_HIP;
 }
@@ -284,13 +292,15 @@ int launch_status() {
 enum KernelId : int {
   kKPartition = 0, kKSlice, kKEmit, kKFinish, kKDirect, kKBatchPlan, kKBatchRun, kKRadixHist, kKRadixScan,
   kKRadixPass, kKCountSlice, kKPartitionMulti, kKSliceMulti, kKEmitMulti, kKFinishMulti, kKMarkAtomic,
-  kKChunkCount, kKChunkScan, kKCount
+  kKChunkCount, kKChunkScan, kKPairsScatter, kKPairsGather, kKPartitionKV, kKSliceKV, kKPairsFinish, kKCount
 };
 const char* const kKernelNames[kKCount] = {"k_partition", "k_slice",      "k_emit",       "k_finish",
                                            "k_direct",    "k_batch_plan", "k_batch_run",  "k_radix_hist",
                                            "k_radix_scan", "k_radix_pass", "k_count_slice",
                                            "k_partition_multi", "k_slice_multi", "k_emit_multi",
-                                           "k_finish_multi", "k_mark_atomic", "k_chunk_count", "k_chunk_scan"};
+                                           "k_finish_multi", "k_mark_atomic", "k_chunk_count", "k_chunk_scan",
+                                           "k_pairs_scatter", "k_pairs_gather", "k_partition_kv", "k_slice_kv",
+                                           "k_pairs_finish"};
 struct PendingTiming {
   int kernel;
   hipEvent_t start, stop;
@@ -1372,6 +1382,147 @@ int bitsort_radix_u64(const uint64_t* keys, uint64_t n, uint32_t key_bits, uint6
 int bitsort_radix_pairs_u32(const uint32_t* keys, const uint32_t* values, uint64_t n, uint32_t key_bits,
                             uint32_t* out_keys, uint32_t* out_values, bitsort_stream_t stream) {
   return radix_on_stream<uint32_t, true>(keys, values, n, key_bits, 0u, out_keys, out_values, stream);
+}
+
+constexpr uint32_t kPairsMaxRangeBits = 30;  // the table route: 4 bytes per possible key, at most 4 GiB
+
+// Plan of a key-value sort.  Records route when a slice of about 2^14 keys
+// (at the input's density) has a bit-vector of at most 2^18 bits: its bits,
+// their word prefixes, its tiles' segments and a window for its values then
+// share one LDS.  Else (small inputs, sparse ranges) the table route, over
+// the plain plan.
+struct PairsPlan {
+  bool records = false;
+  uint32_t rb = 0, sb = 0, nb = 1, tile_log2 = 0, tile_keys = 0, nt = 0;
+  uint32_t ct = 0, cap = 0;   // tiles whose segments k_slice_kv keeps in LDS; its window (values)
+  bool short_units = false;
+  size_t off_info = 0, off_table = 0, off_stg_k = 0, off_stg_v = 0, bytes = 0;
+  Plan plain;                 // table route
+  size_t off_vtable = 0;      // table route: the value table, 4 * 2^rb bytes
+};
+
+void make_pairs_plan(uint64_t n, uint32_t rb, PairsPlan* p) {
+  *p = PairsPlan();
+  p->rb = rb;
+  const uint32_t lg = ceil_log2(n);
+  uint32_t sb = rb + 14u > lg ? rb + 14u - lg : 0u;  // about 2^14 keys per slice
+  sb = std::max({sb, kMinSliceBits, rb > kMaxBucketsLog2 ? rb - kMaxBucketsLog2 : 0u});
+  sb = std::min(sb, rb);
+  if (n > kDirectMaxN && rb > kMinSliceBits && sb <= kPairsMaxSliceBits) {
+    p->records = true;
+    p->sb = sb;
+    p->nb = 1u << (rb - sb);
+    // 2^15-record tiles once there are 2048 slices or more (segments of a
+    // few records each otherwise), 2^14 for other large inputs
+    p->tile_log2 = n >= (1ull << 22) ? (p->nb >= 2048 ? 15u : 14u) : 12u;
+    p->tile_keys = 1u << p->tile_log2;
+    p->nt = static_cast<uint32_t>((n + p->tile_keys - 1) >> p->tile_log2);
+    p->ct = std::min(p->nt, kPairsSegCache);
+    p->cap = pairs_window_words(sb, p->ct);
+    p->short_units = (static_cast<uint64_t>(p->tile_keys) << sb) <= (8ull << rb);
+    p->off_info = kHeaderBytes;
+    p->off_table = align256(p->off_info + 24ull * p->nb);
+    p->off_stg_k = align256(p->off_table + 4ull * p->nt * (p->nb + 1));
+    p->off_stg_v = align256(p->off_stg_k + 4ull * p->nt * p->tile_keys + kStagingPad);
+    p->bytes = align256(p->off_stg_v + 4ull * p->nt * p->tile_keys);
+    return;
+  }
+  make_plan(n, rb, &p->plain);
+  p->off_vtable = align256(p->plain.bytes);
+  p->bytes = p->off_vtable + (4ull << rb);
+}
+
+int run_pairs_records(const PairsPlan& p, const uint32_t* keys, const uint32_t* values, uint64_t n,
+                      uint32_t* out_keys, uint32_t* out_values, void* ws, hipStream_t stream) {
+  char* base = static_cast<char*>(ws);
+  Status* status = reinterpret_cast<Status*>(base);
+  uint64_t* info = reinterpret_cast<uint64_t*>(base + p.off_info);
+  uint32_t* table = reinterpret_cast<uint32_t*>(base + p.off_table);
+  uint32_t* stg_k = reinterpret_cast<uint32_t*>(base + p.off_stg_k);
+  uint32_t* stg_v = reinterpret_cast<uint32_t*>(base + p.off_stg_v);
+  const uint64_t range = 1ull << p.rb;
+  const int vec_ok = ((reinterpret_cast<uintptr_t>(keys) | reinterpret_cast<uintptr_t>(values)) % 16u) == 0 ? 1 : 0;
+  const size_t part_lds = 4ull * (32 + round_up4(p.nb) + p.tile_keys);
+  int rc;
+  {
+    LaunchTimer timer(kKPartitionKV, stream);
+    if (p.tile_log2 == 12)
+      hipLaunchKernelGGL((k_partition_kv<1024, 4>), dim3(p.nt), dim3(1024), part_lds, stream, keys, values, n, range,
+                         p.sb, p.nb, stg_k, stg_v, table, vec_ok);
+    else if (p.tile_log2 == 14)
+      hipLaunchKernelGGL((k_partition_kv<1024, 16>), dim3(p.nt), dim3(1024), part_lds, stream, keys, values, n,
+                         range, p.sb, p.nb, stg_k, stg_v, table, vec_ok);
+    else
+      hipLaunchKernelGGL((k_partition_kv<1024, 32>), dim3(p.nt), dim3(1024), part_lds, stream, keys, values, n,
+                         range, p.sb, p.nb, stg_k, stg_v, table, vec_ok);
+    if ((rc = launch_status()) != BITSORT_OK) return rc;
+  }
+  {
+    LaunchTimer timer(kKSliceKV, stream);
+    auto kernel = p.short_units ? k_slice_kv<kSliceBlock, kSliceUnroll, 16> : k_slice_kv<kSliceBlock, kSliceUnroll, 64>;
+    hipLaunchKernelGGL(kernel, dim3(8u * ((p.nb + 7u) / 8u)), dim3(kSliceBlock), kLdsBytes, stream, stg_k, stg_v,
+                       table, p.nt, p.ct, p.tile_keys, p.sb, p.nb, p.cap, out_keys, out_values, info);
+    if ((rc = launch_status()) != BITSORT_OK) return rc;
+  }
+  LaunchTimer timer(kKPairsFinish, stream);
+  hipLaunchKernelGGL((k_pairs_finish<kSliceBlock>), dim3(1), dim3(kSliceBlock), 0, stream, n, p.nb, info, status,
+                     out_keys, out_values);
+  return launch_status();
+}
+
+int run_pairs_table(const PairsPlan& p, const uint32_t* keys, const uint32_t* values, uint64_t n,
+                    uint32_t* out_keys, uint32_t* out_values, void* ws, hipStream_t stream) {
+  uint32_t* table = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + p.off_vtable);
+  const uint64_t range = 1ull << p.rb;
+  const dim3 grid(static_cast<uint32_t>((n + kPairsPerBlock - 1) / kPairsPerBlock));
+  int rc;
+  {
+    // before the sort, which may write over keys (out_keys == keys)
+    LaunchTimer timer(kKPairsScatter, stream);
+    hipLaunchKernelGGL(k_pairs_scatter, grid, dim3(kPairsBlock), 0, stream, keys, values, n, range, table);
+    if ((rc = launch_status()) != BITSORT_OK) return rc;
+  }
+  // the finish step in the stream: a repeated key's compaction comes before the gather
+  if ((rc = run_plain(p.plain, keys, n, out_keys, ws, stream, kEmit, nullptr, nullptr, nullptr, false)) != BITSORT_OK)
+    return rc;
+  LaunchTimer timer(kKPairsGather, stream);
+  hipLaunchKernelGGL(k_pairs_gather, grid, dim3(kPairsBlock), 0, stream, out_keys, n, range, table, out_values);
+  return launch_status();
+}
+
+int bitsort_pairs_u32(const uint32_t* keys, const uint32_t* values, uint64_t n, uint32_t range_bits,
+                      uint32_t* out_keys, uint32_t* out_values, bitsort_stream_t stream) {
+  int rc = check_args(keys, n, range_bits, out_keys);
+  if (rc != BITSORT_OK) return rc;
+  if (range_bits > kPairsMaxRangeBits) return BITSORT_ERR_INVALID_ARG;
+  if (n > 0) {
+    if (values == nullptr || out_values == nullptr) return BITSORT_ERR_INVALID_ARG;
+    auto meets = [&](const void* a, const void* b) {  // [a, a + 4n) against [b, b + 4n)
+      const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+      return a0 < b0 + 4 * n && b0 < a0 + 4 * n;
+    };
+    if (values != out_values && meets(values, out_values)) return BITSORT_ERR_INVALID_ARG;
+    for (const void* k : {static_cast<const void*>(keys), static_cast<const void*>(out_keys)})
+      for (const void* v : {static_cast<const void*>(values), static_cast<const void*>(out_values)})
+        if (meets(k, v)) return BITSORT_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  StreamCtx& c = ctx_for(stream);
+  c.used = true;
+  if (n == 0) {
+    c.last_empty = true;
+    return BITSORT_OK;
+  }
+  if ((rc = init_kernels()) != BITSORT_OK) return rc;
+  PairsPlan p;
+  make_pairs_plan(n, range_bits, &p);
+  rc = grow(&c.ws, &c.bytes, p.bytes, s, c.external);
+  if (rc != BITSORT_OK) return rc;
+  c.last_empty = false;
+  c.last_atomic = false;
+  return p.records ? run_pairs_records(p, keys, values, n, out_keys, out_values, c.ws, s)
+                   : run_pairs_table(p, keys, values, n, out_keys, out_values, c.ws, s);
 }
 
 int bitsort_i32(const int32_t* keys_s, uint64_t n, uint32_t range_bits, int32_t* out_s, bitsort_stream_t stream) {

@@ -1,0 +1,233 @@
+"""Parity of the bitmap sort of (key, value) records (bitsort_pairs_u32) with
+the oracle's Algorithm 1 on the same records over range_bits bit passes,
+element by element.
+
+With distinct keys the ascending arrangement of the records is unique
+(Theorem 1), so every value must land beside its key.  Repeated keys keep one
+of their values: those cases check the keys and flags against the oracle's
+bitmap sort and each value against the set of values its key came with.
+
+Two routes: the records route (values staged beside their keys, placed by
+rank in an LDS window, or straight to HBM when a slice holds more keys than
+the window) for inputs whose slices of about 2^14 keys span at most 2^18
+bits, and the table route (a value table indexed by key) for small or sparse
+inputs.  Each case states the route it takes, checked through the library's
+kernel timings.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import require_gpu, to_dev, to_np
+from paper_1312_0138_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+@pytest.fixture(scope="module")
+def o():
+    return oracle.default()
+
+
+RECORDS, TABLE = "k_slice_kv", "k_pairs_scatter"
+
+
+def _pairs(keys, values, rb, route=None, **kw):
+    """Sort on the device; with `route`, also check that the kernel naming
+    that route ran."""
+    import paper_1312_0138_amd as bs
+    from paper_1312_0138_amd import _lib
+    k, v = to_dev(keys), to_dev(values)
+    _lib.check(_lib.bitsort_profile_reset(), "profile_reset")
+    _lib.check(_lib.bitsort_profile_enable(True), "profile_enable")
+    try:
+        ok, ov = bs.sort_pairs(k, v, rb, **kw)
+        st = bs.status()
+    finally:
+        _lib.check(_lib.bitsort_profile_enable(False), "profile_enable")
+    rc, prof = _lib.bitsort_profile_read()
+    _lib.check(rc, "profile_read")
+    if route is not None and keys.size:
+        assert route in prof, sorted(prof)
+        assert ({RECORDS, TABLE} - {route}).isdisjoint(prof), sorted(prof)
+    return to_np(ok), to_np(ov), st
+
+
+# table route: one workgroup, a sparse range; records route: 2^17- to
+# 2^14-bit slices, 2^12- and 2^14-key tiles, ragged tails, 16- and 64-key
+# gather units
+@pytest.mark.parametrize("n,rb,route", [(1, 8, TABLE), (1000, 12, TABLE), (4097, 16, TABLE), (2_000_000, 28, TABLE),
+                                        (100_003, 20, RECORDS), (1_000_000, 24, RECORDS), (3_000_000, 23, RECORDS),
+                                        (3_000_001, 22, RECORDS), (5_000_000, 24, RECORDS)])
+def test_distinct_keys(o, n, rb, route):
+    keys = inputs.distinct_uniform(n, rb, 900 + rb)
+    vals = np.random.default_rng(n).integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    got_k, got_v, st = _pairs(keys, vals, rb, route)
+    want_k, want_v = o.bitwise_sort1_pairs(keys, vals, rb)
+    assert st.flags == 0 and st.count == n
+    np.testing.assert_array_equal(got_k, want_k)
+    np.testing.assert_array_equal(got_v, want_v)
+
+
+@pytest.mark.parametrize("path", [1, 2, 3, 4])
+def test_table_route_over_every_emission_path(o, path):
+    """Sparse records (2^-7 of the range) through the table route, with the
+    plain sort's emission path forced each way in turn."""
+    import paper_1312_0138_amd as bs
+    rb, n = 28, 1_500_000
+    keys = inputs.distinct_uniform(n, rb, 31 + path)
+    vals = np.arange(n, dtype=np.uint32)[::-1].copy()
+    want_k, want_v = o.bitwise_sort1_pairs(keys, vals, rb)
+    bs.set_tuning(0, 0, path)
+    try:
+        got_k, got_v, st = _pairs(keys, vals, rb, TABLE)
+    finally:
+        bs.set_tuning(0, 0, 0)
+    assert st.flags == 0 and st.count == n
+    np.testing.assert_array_equal(got_k, want_k)
+    np.testing.assert_array_equal(got_v, want_v)
+
+
+@pytest.mark.parametrize("rb,n", [(22, 700_001), (28, 300_000)])  # records, table route
+def test_in_place(o, rb, n):
+    import paper_1312_0138_amd as bs
+    keys = inputs.distinct_uniform(n, rb, 5)
+    vals = (keys.astype(np.uint64) * 2654435761 % (1 << 32)).astype(np.uint32)
+    k, v = to_dev(keys), to_dev(vals)
+    ok, ov = bs.sort_pairs(k, v, rb, out_keys=k, out_values=v)
+    assert ok.data_ptr() == k.data_ptr() and ov.data_ptr() == v.data_ptr()
+    want_k, want_v = o.bitwise_sort1_pairs(keys, vals, rb)
+    np.testing.assert_array_equal(to_np(k), want_k)
+    np.testing.assert_array_equal(to_np(v), want_v)
+
+
+@pytest.mark.parametrize("rb,n,route", [(12, 3000, TABLE), (24, 900_000, RECORDS), (22, 3_000_000, RECORDS)])
+def test_repeated_and_out_of_range_keys(o, rb, n, route):
+    """Flags and the compacted keys (and values) as the oracle's bitmap sort
+    gives them; each value one of those its key arrived with."""
+    import paper_1312_0138_amd as bs
+    rng = np.random.default_rng(rb)
+    base = inputs.distinct_uniform(n, rb, 70 + rb)
+    dup = rng.choice(base, size=n // 10, replace=False)
+    bad = ((1 << rb) + rng.integers(0, 1 << 8, size=37)).astype(np.uint32)
+    keys = np.concatenate([base, dup, bad])
+    keys = keys[rng.permutation(keys.size)]
+    vals = rng.integers(0, 1 << 32, size=keys.size, dtype=np.uint64).astype(np.uint32)
+    got_k, got_v, st = _pairs(keys, vals, rb, route)
+    want_k, _, _ = o.bitmap_sort(keys, rb)
+    assert st.flags == (bs.STATUS_OUT_OF_RANGE | bs.STATUS_DUPLICATE)
+    assert st.count == want_k.size
+    m = want_k.size
+    np.testing.assert_array_equal(got_k[:m], want_k)
+    # the values each key arrived with, as sorted (key, value) records
+    order = np.lexsort((vals, keys))
+    rk, rv = keys[order], vals[order]
+    lo = np.searchsorted(rk, got_k[:m], side="left")
+    hi = np.searchsorted(rk, got_k[:m], side="right")
+    assert np.all(hi > lo)
+    ok = np.array([got_v[j] in rv[lo[j]:hi[j]] for j in np.nonzero(hi - lo > 1)[0]], dtype=bool)
+    assert ok.all()
+    single = hi - lo == 1
+    np.testing.assert_array_equal(got_v[:m][single], rv[lo[single]])
+
+
+def test_headline_size_values_follow_keys(o):
+    """2^26 distinct keys below 2^28 (the uniform workload's shape) with
+    values a bijection of the keys: the keys as the oracle's bitmap sort
+    gives them and every value equal to its key's image."""
+    import paper_1312_0138_amd as bs
+    rb, n = 28, 1 << 26
+    keys = inputs.distinct_uniform(n, rb, inputs.config_seed(1, 0))
+    img = lambda k: ((k.astype(np.uint64) * 0x9E3779B1) % (1 << 32)).astype(np.uint32) ^ np.uint32(0x5bd1e995)
+    got_k, got_v, st = _pairs(keys, img(keys), rb, RECORDS)
+    want_k, _, _ = o.bitmap_sort(keys, rb)
+    assert st.flags == 0 and st.count == n
+    np.testing.assert_array_equal(got_k, want_k)
+    np.testing.assert_array_equal(got_v, img(want_k))
+
+
+def test_empty_and_reuse(o):
+    """n = 0 leaves the outputs alone and reads back an empty status; the next
+    call on the same stream, smaller than an earlier one, is exact."""
+    import torch
+    import paper_1312_0138_amd as bs
+    e = torch.empty(0, dtype=torch.int32, device="cuda")
+    ok, ov = bs.sort_pairs(e, e.clone(), 20)
+    st = bs.status()
+    assert ok.numel() == 0 and ov.numel() == 0 and st.flags == 0 and st.count == 0
+    for n, rb, route in ((400_000, 26, TABLE), (2_000_000, 22, RECORDS), (300_000, 20, RECORDS), (5000, 14, TABLE)):
+        keys = inputs.distinct_uniform(n, rb, n)
+        vals = np.arange(n, dtype=np.uint32)
+        got_k, got_v, st = _pairs(keys, vals, rb, route)
+        want_k, want_v = o.bitwise_sort1_pairs(keys, vals, rb)
+        assert st.flags == 0 and st.count == n
+        np.testing.assert_array_equal(got_k, want_k)
+        np.testing.assert_array_equal(got_v, want_v)
+
+
+def test_caller_workspace_too_small_is_an_error():
+    """With a caller workspace that holds the plain sort but not the value
+    table, the call returns BITSORT_ERR_NO_MEMORY and allocates nothing."""
+    import torch
+    import paper_1312_0138_amd as bs
+    from paper_1312_0138_amd import _lib
+    n, rb = 100_000, 24
+    ws = torch.empty(bs.workspace_bytes(n, rb), dtype=torch.uint8, device="cuda")
+    keys = to_dev(inputs.distinct_uniform(n, rb, 3))
+    vals = to_dev(np.arange(n, dtype=np.uint32))
+    ok, ov = torch.empty_like(keys), torch.empty_like(vals)
+    s = torch.cuda.current_stream().cuda_stream
+    assert _lib.bitsort_set_workspace(ws.data_ptr(), ws.numel(), s) == _lib.BITSORT_OK
+    try:
+        rc = _lib.bitsort_pairs_u32(keys.data_ptr(), vals.data_ptr(), n, rb, ok.data_ptr(), ov.data_ptr(), s)
+        assert rc == _lib.BITSORT_ERR_NO_MEMORY
+    finally:
+        assert _lib.bitsort_set_workspace(0, 0, s) == _lib.BITSORT_OK
+
+
+def test_slices_past_the_window(o):
+    """Three slices holding more distinct keys than the LDS window (2^16-bit
+    slices at this density, a window of about 34,700 values) write their
+    values and keys straight to HBM; the rest go through the window."""
+    rb, sb = 24, 16
+    rng = np.random.default_rng(44)
+    bg = inputs.distinct_uniform(3_000_000, rb, 45).astype(np.uint64)
+    heavy = np.array([3, 100, 255], dtype=np.uint64)
+    bg = bg[~np.isin(bg >> np.uint64(sb), heavy)]
+    parts = [bg] + [(h << np.uint64(sb)) + rng.choice(1 << sb, size=c, replace=False).astype(np.uint64)
+                    for h, c in zip(heavy, (40_000, 65_536, 50_000))]
+    keys = np.concatenate(parts).astype(np.uint32)
+    keys = keys[rng.permutation(keys.size)]
+    assert 1 << 21 < keys.size <= 1 << 22  # 2^16-bit slices at range 2^24
+    vals = rng.integers(0, 1 << 32, size=keys.size, dtype=np.uint64).astype(np.uint32)
+    got_k, got_v, st = _pairs(keys, vals, rb, RECORDS)
+    want_k, want_v = o.bitwise_sort1_pairs(keys, vals, rb)
+    assert st.flags == 0 and st.count == keys.size
+    np.testing.assert_array_equal(got_k, want_k)
+    np.testing.assert_array_equal(got_v, want_v)
+
+
+@pytest.mark.parametrize("rb,n,route", [(24, 1_000_003, RECORDS), (28, 300_001, TABLE)])
+def test_unaligned_arrays(o, rb, n, route):
+    """Keys and values starting 4 bytes past a 16-byte boundary (the
+    partition's element-wise loads), outputs likewise."""
+    import torch
+    import paper_1312_0138_amd as bs
+    keys = inputs.distinct_uniform(n, rb, 8)
+    vals = np.arange(n, dtype=np.uint32) * np.uint32(3)
+    k = to_dev(np.concatenate([[0], keys]).astype(np.uint32))[1:]
+    v = to_dev(np.concatenate([[0], vals]).astype(np.uint32))[1:]
+    ok = torch.empty(n + 1, dtype=torch.int32, device="cuda")[1:]
+    ov = torch.empty(n + 1, dtype=torch.int32, device="cuda")[1:]
+    assert k.data_ptr() % 16 and v.data_ptr() % 16 and ok.data_ptr() % 16
+    bs.sort_pairs(k, v, rb, out_keys=ok, out_values=ov)
+    st = bs.status()
+    want_k, want_v = o.bitwise_sort1_pairs(keys, vals, rb)
+    assert st.flags == 0 and st.count == n
+    np.testing.assert_array_equal(to_np(ok), want_k)
+    np.testing.assert_array_equal(to_np(ov), want_v)

@@ -99,6 +99,18 @@ def test_host_argument_checks(lib):
     assert E.bitsort_radix_pairs_u32(fake, big, 100, 32, fake + 4096, fake + 8, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_radix_pairs_u32(fake, 0, 100, 32, fake + 4096, big, 0) == E.BITSORT_ERR_INVALID_ARG
     assert E.bitsort_radix_u32_ws(fake, 10, 32, fake + 4096, fake, 16, 0) == E.BITSORT_ERR_NO_MEMORY
+    # key-value records on the bitmap path: the four arrays 4 MiB apart unless stated
+    k, v, ok, ov = fake, fake + (4 << 20), fake + (8 << 20), fake + (12 << 20)
+    P = E.bitsort_pairs_u32
+    assert P(k, v, 100, 31, ok, ov, 0) == E.BITSORT_ERR_INVALID_ARG     # value table past 2^30 words
+    assert P(k, v, 100, 6, ok, ov, 0) == E.BITSORT_ERR_TOO_LARGE        # 100 keys cannot be distinct below 2^6
+    assert P(k, 0, 100, 20, ok, ov, 0) == E.BITSORT_ERR_INVALID_ARG     # no values
+    assert P(k, v, 100, 20, ok, 0, 0) == E.BITSORT_ERR_INVALID_ARG      # nowhere to put them
+    assert P(k, v, 100, 20, ok, v + 4, 0) == E.BITSORT_ERR_INVALID_ARG  # values and out_values partly overlap
+    assert P(k, v, 100, 20, ok, k, 0) == E.BITSORT_ERR_INVALID_ARG      # out_values over the keys
+    assert P(k, ok + 200, 100, 20, ok, ov, 0) == E.BITSORT_ERR_INVALID_ARG  # values meet out_keys
+    assert P(k, v, 100, 20, k + 4, ov, 0) == E.BITSORT_ERR_INVALID_ARG  # keys partly under out_keys
+    assert P(0, 0, 0, 20, 0, 0, 0) == E.BITSORT_OK                      # nothing to sort, nothing touched
 
 
 def test_plan_shapes(lib):
