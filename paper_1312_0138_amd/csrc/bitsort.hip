@@ -1386,17 +1386,18 @@ int bitsort_radix_pairs_u32(const uint32_t* keys, const uint32_t* values, uint64
 
 constexpr uint32_t kPairsMaxRangeBits = 30;  // the table route: 4 bytes per possible key, at most 4 GiB
 
-// Plan of a key-value sort.  Records route when a slice of about 2^14 keys
-// (at the input's density) has a bit-vector of at most 2^18 bits: its bits,
-// their word prefixes, its tiles' segments and a window for its values then
-// share one LDS.  Else (small inputs, sparse ranges) the table route, over
-// the plain plan.
+// Plan of a key-value sort.  Records route when some slice width of at most
+// 2^18 bits (and at most 4096 slices) holds an expected slice's records,
+// with 1/8 to spare, in the LDS that its bits and their word prefixes leave;
+// the widest such width is taken.  Inputs too dense for any take the
+// narrowest width and the route's second gather.  Small inputs, and sparse
+// ranges (no width up to 2^18 bits holds enough keys to pay for a slice),
+// take the table route, over the plain plan.
 struct PairsPlan {
   bool records = false;
   uint32_t rb = 0, sb = 0, nb = 1, tile_log2 = 0, tile_keys = 0, nt = 0;
-  uint32_t ct = 0, cap = 0;   // tiles whose segments k_slice_kv keeps in LDS; its window (values)
   bool short_units = false;
-  size_t off_info = 0, off_table = 0, off_stg_k = 0, off_stg_v = 0, bytes = 0;
+  size_t off_info = 0, off_table = 0, off_stg = 0, bytes = 0;
   Plan plain;                 // table route
   size_t off_vtable = 0;      // table route: the value table, 4 * 2^rb bytes
 };
@@ -1404,11 +1405,21 @@ struct PairsPlan {
 void make_pairs_plan(uint64_t n, uint32_t rb, PairsPlan* p) {
   *p = PairsPlan();
   p->rb = rb;
+  const uint32_t lo = std::max(kMinSliceBits, rb > kMaxBucketsLog2 ? rb - kMaxBucketsLog2 : 0u);
+  const uint32_t hi = std::min(kPairsMaxSliceBits, rb);
+  // a slice needs about 2^13 keys to pay for itself: below that (sparse
+  // ranges), the table route
   const uint32_t lg = ceil_log2(n);
-  uint32_t sb = rb + 14u > lg ? rb + 14u - lg : 0u;  // about 2^14 keys per slice
-  sb = std::max({sb, kMinSliceBits, rb > kMaxBucketsLog2 ? rb - kMaxBucketsLog2 : 0u});
-  sb = std::min(sb, rb);
-  if (n > kDirectMaxN && rb > kMinSliceBits && sb <= kPairsMaxSliceBits) {
+  const bool enough = lg + hi >= rb + 13u;
+  if (n > kDirectMaxN && rb > kMinSliceBits && lo <= hi && enough) {
+    uint32_t sb = lo;
+    for (uint32_t w = hi; w >= lo; --w) {
+      const uint64_t expect = ((n << w) >> rb) + 1u;  // records per slice, uniform keys
+      if (expect + expect / 8u <= pairs_record_cap(w)) {
+        sb = w;
+        break;
+      }
+    }
     p->records = true;
     p->sb = sb;
     p->nb = 1u << (rb - sb);
@@ -1417,14 +1428,11 @@ void make_pairs_plan(uint64_t n, uint32_t rb, PairsPlan* p) {
     p->tile_log2 = n >= (1ull << 22) ? (p->nb >= 2048 ? 15u : 14u) : 12u;
     p->tile_keys = 1u << p->tile_log2;
     p->nt = static_cast<uint32_t>((n + p->tile_keys - 1) >> p->tile_log2);
-    p->ct = std::min(p->nt, kPairsSegCache);
-    p->cap = pairs_window_words(sb, p->ct);
     p->short_units = (static_cast<uint64_t>(p->tile_keys) << sb) <= (8ull << rb);
     p->off_info = kHeaderBytes;
     p->off_table = align256(p->off_info + 24ull * p->nb);
-    p->off_stg_k = align256(p->off_table + 4ull * p->nt * (p->nb + 1));
-    p->off_stg_v = align256(p->off_stg_k + 4ull * p->nt * p->tile_keys + kStagingPad);
-    p->bytes = align256(p->off_stg_v + 4ull * p->nt * p->tile_keys);
+    p->off_stg = align256(p->off_table + 4ull * p->nt * (p->nb + 1));
+    p->bytes = align256(p->off_stg + 8ull * p->nt * p->tile_keys);
     return;
   }
   make_plan(n, rb, &p->plain);
@@ -1438,30 +1446,30 @@ int run_pairs_records(const PairsPlan& p, const uint32_t* keys, const uint32_t* 
   Status* status = reinterpret_cast<Status*>(base);
   uint64_t* info = reinterpret_cast<uint64_t*>(base + p.off_info);
   uint32_t* table = reinterpret_cast<uint32_t*>(base + p.off_table);
-  uint32_t* stg_k = reinterpret_cast<uint32_t*>(base + p.off_stg_k);
-  uint32_t* stg_v = reinterpret_cast<uint32_t*>(base + p.off_stg_v);
+  uint32_t* stg = reinterpret_cast<uint32_t*>(base + p.off_stg);
   const uint64_t range = 1ull << p.rb;
   const int vec_ok = ((reinterpret_cast<uintptr_t>(keys) | reinterpret_cast<uintptr_t>(values)) % 16u) == 0 ? 1 : 0;
   const size_t part_lds = 4ull * (32 + round_up4(p.nb) + p.tile_keys);
+  const uint32_t grid = 8u * ((p.nt + 7u) / 8u);  // the 8-way XCD mapping of tiles
   int rc;
   {
     LaunchTimer timer(kKPartitionKV, stream);
     if (p.tile_log2 == 12)
-      hipLaunchKernelGGL((k_partition_kv<1024, 4>), dim3(p.nt), dim3(1024), part_lds, stream, keys, values, n, range,
-                         p.sb, p.nb, stg_k, stg_v, table, vec_ok);
+      hipLaunchKernelGGL((k_partition_kv<1024, 4>), dim3(grid), dim3(1024), part_lds, stream, keys, values, n, range,
+                         p.sb, p.nb, p.nt, stg, table, vec_ok);
     else if (p.tile_log2 == 14)
-      hipLaunchKernelGGL((k_partition_kv<1024, 16>), dim3(p.nt), dim3(1024), part_lds, stream, keys, values, n,
-                         range, p.sb, p.nb, stg_k, stg_v, table, vec_ok);
+      hipLaunchKernelGGL((k_partition_kv<1024, 16>), dim3(grid), dim3(1024), part_lds, stream, keys, values, n,
+                         range, p.sb, p.nb, p.nt, stg, table, vec_ok);
     else
-      hipLaunchKernelGGL((k_partition_kv<1024, 32>), dim3(p.nt), dim3(1024), part_lds, stream, keys, values, n,
-                         range, p.sb, p.nb, stg_k, stg_v, table, vec_ok);
+      hipLaunchKernelGGL((k_partition_kv<1024, 32>), dim3(grid), dim3(1024), part_lds, stream, keys, values, n,
+                         range, p.sb, p.nb, p.nt, stg, table, vec_ok);
     if ((rc = launch_status()) != BITSORT_OK) return rc;
   }
   {
     LaunchTimer timer(kKSliceKV, stream);
     auto kernel = p.short_units ? k_slice_kv<kSliceBlock, kSliceUnroll, 16> : k_slice_kv<kSliceBlock, kSliceUnroll, 64>;
-    hipLaunchKernelGGL(kernel, dim3(8u * ((p.nb + 7u) / 8u)), dim3(kSliceBlock), kLdsBytes, stream, stg_k, stg_v,
-                       table, p.nt, p.ct, p.tile_keys, p.sb, p.nb, p.cap, out_keys, out_values, info);
+    hipLaunchKernelGGL(kernel, dim3(8u * ((p.nb + 7u) / 8u)), dim3(kSliceBlock), kLdsBytes, stream,
+                       reinterpret_cast<const uint2*>(stg), table, p.nt, p.tile_keys, p.sb, p.nb, out_keys, out_values, info);
     if ((rc = launch_status()) != BITSORT_OK) return rc;
   }
   LaunchTimer timer(kKPairsFinish, stream);

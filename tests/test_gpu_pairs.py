@@ -7,11 +7,11 @@ With distinct keys the ascending arrangement of the records is unique
 of their values: those cases check the keys and flags against the oracle's
 bitmap sort and each value against the set of values its key came with.
 
-Two routes: the records route (values staged beside their keys, placed by
-rank in an LDS window, or straight to HBM when a slice holds more keys than
-the window) for inputs whose slices of about 2^14 keys span at most 2^18
-bits, and the table route (a value table indexed by key) for small or sparse
-inputs.  Each case states the route it takes, checked through the library's
+Two routes: the records route (records staged by slice, gathered into LDS
+with the slice's bit-vector and placed by rank; a slice with more records
+than LDS holds gathers them again and writes straight to HBM) for inputs
+with about 2^13 keys or more per 2^18-bit slice, and the table route (a value
+table indexed by key) for small or sparse inputs.  Each case states the route it takes, checked through the library's
 kernel timings.
 """
 import numpy as np
@@ -191,9 +191,9 @@ def test_caller_workspace_too_small_is_an_error():
 
 
 def test_slices_past_the_window(o):
-    """Three slices holding more distinct keys than the LDS window (2^16-bit
-    slices at this density, a window of about 34,700 values) write their
-    values and keys straight to HBM; the rest go through the window."""
+    """Three slices holding more records than LDS has room for (2^16-bit
+    slices at this density, room for 18,396 records) gather them again and
+    write values and keys straight to HBM; the rest go through LDS."""
     rb, sb = 24, 16
     rng = np.random.default_rng(44)
     bg = inputs.distinct_uniform(3_000_000, rb, 45).astype(np.uint64)
