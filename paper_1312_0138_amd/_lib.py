@@ -311,10 +311,10 @@ def bitsort_profile_reset() -> int:
 
 def bitsort_profile_read():
     """-> (rc, {kernel: (launches, total_ms)})."""
-    arr = (ProfileEntry * 16)()
+    arr = (ProfileEntry * 64)()
     n = ctypes.c_int()
-    rc = lib().bitsort_profile_read(arr, 16, ctypes.byref(n))
-    return rc, {arr[i].kernel.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(n.value, 16))}
+    rc = lib().bitsort_profile_read(arr, 64, ctypes.byref(n))
+    return rc, {arr[i].kernel.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(n.value, 64))}
 
 
 def bitsort_graph_create_u32(keys: int, n: int, range_bits: int, out: int):
