@@ -231,3 +231,78 @@ def test_unaligned_arrays(o, rb, n, route):
     assert st.flags == 0 and st.count == n
     np.testing.assert_array_equal(to_np(ok), want_k)
     np.testing.assert_array_equal(to_np(ov), want_v)
+
+
+def _dense_slice(keys_bg, rb, sb, slice_id, count, seed):
+    """keys_bg without slice `slice_id`'s keys, plus `count` distinct keys of it."""
+    k = keys_bg.astype(np.uint64)
+    k = k[(k >> np.uint64(sb)) != np.uint64(slice_id)]
+    rng = np.random.default_rng(seed)
+    extra = (np.uint64(slice_id) << np.uint64(sb)) + rng.choice(1 << sb, size=count, replace=False).astype(np.uint64)
+    out = np.concatenate([k, extra]).astype(np.uint32)
+    return out[rng.permutation(out.size)]
+
+
+# 4096 slices of 2^15 bits over 2^27 and 2^15-record tiles: a tile holds
+# about 8 records of a slice, and each tile's first 16 are gathered into
+# registers.  Slice 7 at 1.5 times the density leaves a few hundred records
+# past their tile's 16th (kept in LDS beside the windows); slice 9 at 2.2
+# times leaves thousands, more than that area keeps (the slice takes the
+# general walk, its records in LDS); slice 11 at 3 times holds more records
+# than LDS (the second gather).  The ragged case is compared with the
+# oracle's Algorithm 1 on the records; the others, at the same size, with its
+# bitmap sort for the keys and with values that are a bijection of the keys.
+def _img(k):
+    return ((k.astype(np.uint64) * 0x9E3779B1) % (1 << 32)).astype(np.uint32) ^ np.uint32(0x2545F491)
+
+
+@pytest.mark.parametrize("case", ["ragged", "uniform", "spill", "general", "regather"])
+def test_register_route(o, case):
+    rb, sb = 27, 15
+    n = (1 << 25) - {"ragged": 12345, "uniform": 0}.get(case, 60_000)  # room for the dense slices
+    keys = inputs.distinct_uniform(n, rb, 61)
+    dense = {"spill": [(7, 12288)], "general": [(7, 12288), (9, 18000)], "regather": [(9, 18000), (11, 24576)]}
+    for slice_id, count in dense.get(case, []):
+        keys = _dense_slice(keys, rb, sb, slice_id, count, 62 + slice_id)
+    assert (1 << 24) < keys.size <= (1 << 25)
+    if case == "ragged":
+        vals = np.random.default_rng(64).integers(0, 1 << 32, size=keys.size, dtype=np.uint64).astype(np.uint32)
+        got_k, got_v, st = _pairs(keys, vals, rb, RECORDS)
+        want_k, want_v = o.bitwise_sort1_pairs(keys, vals, rb)
+    else:
+        got_k, got_v, st = _pairs(keys, _img(keys), rb, RECORDS)
+        want_k, _, _ = o.bitmap_sort(keys, rb)
+        want_v = _img(want_k)
+    assert st.flags == 0 and st.count == keys.size
+    np.testing.assert_array_equal(got_k, want_k)
+    np.testing.assert_array_equal(got_v, want_v)
+
+
+def test_register_route_repeated_and_out_of_range_keys(o):
+    """The register route with repeated keys (their records share a rank) and
+    keys past the range: flags, compacted keys as the oracle's bitmap sort,
+    and each value one its key arrived with."""
+    import paper_1312_0138_amd as bs
+    rb = 27
+    rng = np.random.default_rng(65)
+    base = inputs.distinct_uniform((1 << 25) - 300_000, rb, 66)
+    dup = rng.choice(base, size=250_000, replace=False)
+    bad = ((1 << rb) + rng.integers(0, 1 << 10, size=500)).astype(np.uint32)
+    keys = np.concatenate([base, dup, bad])
+    keys = keys[rng.permutation(keys.size)]
+    vals = rng.integers(0, 1 << 32, size=keys.size, dtype=np.uint64).astype(np.uint32)
+    got_k, got_v, st = _pairs(keys, vals, rb, RECORDS)
+    want_k, _, _ = o.bitmap_sort(keys, rb)
+    assert st.flags == (bs.STATUS_OUT_OF_RANGE | bs.STATUS_DUPLICATE)
+    m = want_k.size
+    assert st.count == m
+    np.testing.assert_array_equal(got_k[:m], want_k)
+    order = np.lexsort((vals, keys))
+    rk, rv = keys[order], vals[order]
+    lo = np.searchsorted(rk, got_k[:m], side="left")
+    hi = np.searchsorted(rk, got_k[:m], side="right")
+    single = hi - lo == 1
+    np.testing.assert_array_equal(got_v[:m][single], rv[lo[single]])
+    multi = np.nonzero(~single)[0]
+    assert multi.size > 1000
+    assert all(got_v[j] in rv[lo[j]:hi[j]] for j in multi)
