@@ -12,9 +12,10 @@ and the CPU oracle timed on this host's cores as a reported baseline.
 
 With no --workload, the headline is plain-small (10^6 keys, the workload the
 roofline target is set on) and the same JSON line carries, under "extras",
-plain-uniform (value and roofline fractions), the batch workload (one batched
-launch against 4096 plain launches, identical results) and the serving trace
-(throughput, p50/p99 latency); --no-extras leaves them out.
+plain-uniform (value and roofline fractions), both through the atomic-OR
+mark, bitmap-pairs (the 2^26 keys with a value each), the batch workload (one
+batched launch against 4096 plain launches, identical results) and the
+serving trace (throughput, p50/p99 latency); --no-extras leaves them out.
 
 Workloads:
   plain-uniform   2^26 distinct keys uniform without replacement in [0, 2^28)
@@ -705,9 +706,10 @@ def main():
 
 
 def bench_extras(args):
-    """The rest of the metric beside the headline: the 2^26-key workload, the
-    batch against per-array launches, and the serving trace (each its own
-    run; CPU baselines left to the single-workload runs)."""
+    """The rest of the metric beside the headline: the 2^26-key workload (also
+    through the atomic-OR mark, and as key-value records), the batch against
+    per-array launches, and the serving trace (each its own run; CPU
+    baselines left to the single-workload runs)."""
     import copy
     sub = copy.copy(args)
     sub.no_cpu_baseline = True
@@ -728,6 +730,9 @@ def bench_extras(args):
                       "roofline": r["roofline"], "roofline_path": r["roofline_path"], "kernels": r["kernels"]}
         print(f"extras: atomic {wl} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
+    kv = bench_plain(sub, "bitmap-pairs")
+    print(f"extras: bitmap-pairs done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
     batch = bench_batch(sub)
     print(f"extras: batch done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -738,6 +743,9 @@ def bench_extras(args):
                           "steps": big["steps"], "config": big["config"], "roofline": big["roofline"],
                           "roofline_path": big["roofline_path"], "kernels": big["kernels"]},
         "atomic_mark": atomic,
+        "bitmap-pairs": {"value": kv["value"], "unit": "Gkeys/s", "ms_per_step": kv["ms_per_step"],
+                         "steps": kv["steps"], "config": kv["config"], "roofline": kv["roofline"],
+                         "roofline_path": kv["roofline_path"], "kernels": kv["kernels"]},
         "batch": {"value": batch["value"], "unit": "Gkeys/s", "config": batch["config"],
                   "batched": batch["batched"], "batched_graph": batch["batched_graph"],
                   "plain_loop": batch["plain_loop"], "pointer_array": batch["pointer_array"],
