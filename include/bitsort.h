@@ -396,18 +396,23 @@ int bitsort_radix_pairs_u32(const uint32_t *keys, const uint32_t *values, uint64
  * record ordered by its key, sorted by the marking, counting and emission of
  * bitsort_u32 (Table I, Examples 2-3, 6 and 1; Theorem 1: with distinct keys
  * the ascending arrangement, values included, is unique).
- *   out_keys      as bitsort_u32 writes them;
- *   out_values[j] the value that came with out_keys[j].
- * The values ride on a table of 2^range_bits words indexed by key, kept in
- * the stream's workspace (plain workspace plus 4 * 2^range_bits bytes):
- * values[i] goes to table[keys[i]] before the sort and out_values[j] =
- * table[out_keys[j]] after it.  range_bits <= 30 (BITSORT_ERR_INVALID_ARG
- * otherwise).  Status (bitsort_get_status) as for bitsort_u32; a repeated key
- * keeps one of its values (which one is unspecified); entries past the
- * status count are unspecified, as for the keys.  out_keys may equal keys and
- * out_values may equal values; any other overlap among the four arrays, or a
- * null array with n > 0, is BITSORT_ERR_INVALID_ARG.  Stream-ordered,
- * allocation only when the workspace grows.
+ *   keys, values      device arrays of n uint32 each, record i = (keys[i],
+ *                     values[i]); keys below 2^range_bits;
+ *   out_keys          as bitsort_u32 writes them;
+ *   out_values[j]     the value that came with out_keys[j].
+ * A record goes to its key's rank among the distinct keys.  Dense inputs
+ * (about 2^13 keys or more per 2^18 possible keys) stage the records by slice
+ * and place each value at its key's rank in LDS (workspace about 8n bytes);
+ * smaller or sparser ones carry the values on a table of one word per
+ * possible key (the plain workspace plus 4 * 2^range_bits bytes), where
+ * bitsort_radix_pairs_u32 is usually faster.  range_bits <= 30
+ * (BITSORT_ERR_INVALID_ARG otherwise).  Status (bitsort_get_status) as for
+ * bitsort_u32; a repeated key keeps one of its values (which one is
+ * unspecified); entries past the status count are unspecified, as for the
+ * keys.  out_keys may equal keys and out_values may equal values; any other
+ * overlap among the four arrays, or a null array with n > 0, is
+ * BITSORT_ERR_INVALID_ARG.  Stream-ordered, allocation only when the
+ * workspace grows.
  */
 int bitsort_pairs_u32(const uint32_t *keys, const uint32_t *values, uint64_t n, uint32_t range_bits,
                       uint32_t *out_keys, uint32_t *out_values, bitsort_stream_t stream);
