@@ -400,12 +400,12 @@ int bitsort_radix_pairs_u32(const uint32_t *keys, const uint32_t *values, uint64
  *                     values[i]); keys below 2^range_bits;
  *   out_keys          as bitsort_u32 writes them;
  *   out_values[j]     the value that came with out_keys[j].
- * A record goes to its key's rank among the distinct keys.  Dense inputs
- * (about 2^13 keys or more per 2^18 possible keys) stage the records by slice
- * and place each value at its key's rank in LDS (workspace about 8n bytes);
+ * A record goes to its key's rank among the distinct keys.  Inputs of more
+ * than 8192 keys at a density above 1/256 stage the records by slice and
+ * place each value at its key's rank in LDS (workspace about 8n bytes);
  * smaller or sparser ones carry the values on a table of one word per
- * possible key (the plain workspace plus 4 * 2^range_bits bytes), where
- * bitsort_radix_pairs_u32 is usually faster.  range_bits <= 30
+ * possible key (the plain workspace plus 4 * 2^range_bits bytes, touched
+ * only where keys fall), where bitsort_radix_pairs_u32 can be faster.  range_bits <= 30
  * (BITSORT_ERR_INVALID_ARG otherwise).  Status (bitsort_get_status) as for
  * bitsort_u32; a repeated key keeps one of its values (which one is
  * unspecified); entries past the status count are unspecified, as for the

@@ -7,11 +7,11 @@ With distinct keys the ascending arrangement of the records is unique
 of their values: those cases check the keys and flags against the oracle's
 bitmap sort and each value against the set of values its key came with.
 
-Two routes: the records route (records staged by slice, gathered into LDS
-with the slice's bit-vector and placed by rank; a slice with more records
-than LDS holds gathers them again and writes straight to HBM) for inputs
-with about 2^13 keys or more per 2^18-bit slice, and the table route (a value
-table indexed by key) for small or sparse inputs.  Each case states the route it takes, checked through the library's
+Two routes: the records route (records staged by slice, gathered with the
+slice's bit-vector and placed by rank; a slice with more records than LDS
+holds gathers them again and writes straight to HBM) for more than 8192 keys
+at a density above 1/256, and the table route (a value table indexed by key)
+for smaller or sparser inputs.  Each case states the route it takes, checked through the library's
 kernel timings.
 """
 import numpy as np
@@ -58,12 +58,14 @@ def _pairs(keys, values, rb, route=None, **kw):
     return to_np(ok), to_np(ov), st
 
 
-# table route: one workgroup, a sparse range; records route: 2^17- to
-# 2^14-bit slices, 2^12- and 2^14-key tiles, ragged tails, 16- and 64-key
-# gather units
-@pytest.mark.parametrize("n,rb,route", [(1, 8, TABLE), (1000, 12, TABLE), (4097, 16, TABLE), (2_000_000, 28, TABLE),
-                                        (100_003, 20, RECORDS), (1_000_000, 24, RECORDS), (3_000_000, 23, RECORDS),
-                                        (3_000_001, 22, RECORDS), (5_000_000, 24, RECORDS)])
+# table route: one workgroup, sparse ranges (a 4 GiB table at 2^30, touched
+# only where keys fall); records route: 2^18- to 2^14-bit slices, 2^12-,
+# 2^14- and 2^15-key tiles, ragged tails, 16- and 64-key gather units, and a
+# density of 1/128 (4096 slices of 2^18 bits, about 2048 records each)
+@pytest.mark.parametrize("n,rb,route", [(1, 8, TABLE), (1000, 12, TABLE), (4097, 16, TABLE), (1000, 30, TABLE),
+                                        (1_000_000, 30, TABLE), (2_000_000, 28, RECORDS), (100_003, 20, RECORDS),
+                                        (1_000_000, 24, RECORDS), (3_000_000, 23, RECORDS), (3_000_001, 22, RECORDS),
+                                        (5_000_000, 24, RECORDS), (4_200_000, 29, RECORDS)])
 def test_distinct_keys(o, n, rb, route):
     keys = inputs.distinct_uniform(n, rb, 900 + rb)
     vals = np.random.default_rng(n).integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
@@ -76,10 +78,10 @@ def test_distinct_keys(o, n, rb, route):
 
 @pytest.mark.parametrize("path", [1, 2, 3, 4])
 def test_table_route_over_every_emission_path(o, path):
-    """Sparse records (2^-7 of the range) through the table route, with the
-    plain sort's emission path forced each way in turn."""
+    """Sparse records (about 2^-9 of the range) through the table route, with
+    the plain sort's emission path forced each way in turn."""
     import paper_1312_0138_amd as bs
-    rb, n = 28, 1_500_000
+    rb, n = 28, 500_000
     keys = inputs.distinct_uniform(n, rb, 31 + path)
     vals = np.arange(n, dtype=np.uint32)[::-1].copy()
     want_k, want_v = o.bitwise_sort1_pairs(keys, vals, rb)
@@ -160,7 +162,7 @@ def test_empty_and_reuse(o):
     ok, ov = bs.sort_pairs(e, e.clone(), 20)
     st = bs.status()
     assert ok.numel() == 0 and ov.numel() == 0 and st.flags == 0 and st.count == 0
-    for n, rb, route in ((400_000, 26, TABLE), (2_000_000, 22, RECORDS), (300_000, 20, RECORDS), (5000, 14, TABLE)):
+    for n, rb, route in ((200_000, 26, TABLE), (2_000_000, 22, RECORDS), (300_000, 20, RECORDS), (5000, 14, TABLE)):
         keys = inputs.distinct_uniform(n, rb, n)
         vals = np.arange(n, dtype=np.uint32)
         got_k, got_v, st = _pairs(keys, vals, rb, route)
