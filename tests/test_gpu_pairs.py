@@ -61,11 +61,12 @@ def _pairs(keys, values, rb, route=None, **kw):
 # table route: one workgroup, sparse ranges (a 4 GiB table at 2^30, touched
 # only where keys fall); records route: 2^18- to 2^14-bit slices, 2^12-,
 # 2^14- and 2^15-key tiles, ragged tails, 16- and 64-key gather units, and a
-# density of 1/128 (4096 slices of 2^18 bits, about 2048 records each)
+# density of 1/128 at 2^29 and 2^30 (2048 and 4096 slices of 2^18 bits, about
+# 2048 records each; the second with 8-record segments, on the register route)
 @pytest.mark.parametrize("n,rb,route", [(1, 8, TABLE), (1000, 12, TABLE), (4097, 16, TABLE), (1000, 30, TABLE),
                                         (1_000_000, 30, TABLE), (2_000_000, 28, RECORDS), (100_003, 20, RECORDS),
                                         (1_000_000, 24, RECORDS), (3_000_000, 23, RECORDS), (3_000_001, 22, RECORDS),
-                                        (5_000_000, 24, RECORDS), (4_200_000, 29, RECORDS)])
+                                        (5_000_000, 24, RECORDS), (4_200_000, 29, RECORDS), (8_400_000, 30, RECORDS)])
 def test_distinct_keys(o, n, rb, route):
     keys = inputs.distinct_uniform(n, rb, 900 + rb)
     vals = np.random.default_rng(n).integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
