@@ -309,3 +309,34 @@ def test_register_route_repeated_and_out_of_range_keys(o):
     multi = np.nonzero(~single)[0]
     assert multi.size > 1000
     assert all(got_v[j] in rv[lo[j]:hi[j]] for j in multi)
+
+
+@pytest.mark.parametrize("n,rb,route", [(1_000_000, 24, RECORDS), (300_000, 28, TABLE)])
+def test_side_stream_and_caller_workspace(o, n, rb, route):
+    """On a side stream, first in the library's own workspace, then in a
+    caller workspace large enough for the route (records: about 8n bytes and
+    the tile table; table: the plain workspace and 4 * 2^range_bits bytes):
+    both exact, statuses read on that stream."""
+    import torch
+    import paper_1312_0138_amd as bs
+    keys = inputs.distinct_uniform(n, rb, 17)
+    vals = np.random.default_rng(18).integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    want_k, want_v = o.bitwise_sort1_pairs(keys, vals, rb)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        k, v = to_dev(keys), to_dev(vals)
+        ok, ov = bs.sort_pairs(k, v, rb, stream=s)
+        st = bs.status(s)
+        assert st.flags == 0 and st.count == n
+        np.testing.assert_array_equal(to_np(ok), want_k)
+        np.testing.assert_array_equal(to_np(ov), want_v)
+        ws = torch.empty(16 * n + (4 << rb) + (64 << 20), dtype=torch.uint8, device="cuda")
+        bs.set_workspace(ws, stream=s)
+        try:
+            ok2, ov2 = bs.sort_pairs(k, v, rb, stream=s)
+            st = bs.status(s)
+        finally:
+            bs.set_workspace(None, stream=s)
+        assert st.flags == 0 and st.count == n
+        np.testing.assert_array_equal(to_np(ok2), want_k)
+        np.testing.assert_array_equal(to_np(ov2), want_v)
