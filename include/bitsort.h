@@ -412,7 +412,8 @@ int bitsort_radix_pairs_u32(const uint32_t *keys, const uint32_t *values, uint64
  * keys.  out_keys may equal keys and out_values may equal values; any other
  * overlap among the four arrays, or a null array with n > 0, is
  * BITSORT_ERR_INVALID_ARG.  Stream-ordered, allocation only when the
- * workspace grows.
+ * workspace grows: once a call has grown the stream's workspace, later calls
+ * of that size on the stream can be captured into a HIP graph.
  */
 int bitsort_pairs_u32(const uint32_t *keys, const uint32_t *values, uint64_t n, uint32_t range_bits,
                       uint32_t *out_keys, uint32_t *out_values, bitsort_stream_t stream);

@@ -340,3 +340,39 @@ def test_side_stream_and_caller_workspace(o, n, rb, route):
         assert st.flags == 0 and st.count == n
         np.testing.assert_array_equal(to_np(ok2), want_k)
         np.testing.assert_array_equal(to_np(ov2), want_v)
+
+
+@pytest.mark.parametrize("n,rb,route", [(1_000_000, 24, RECORDS), (300_000, 28, TABLE)])
+def test_captured_graph_replays(o, n, rb, route):
+    """bitsort_pairs_u32 captured by torch into a HIP graph on a stream whose
+    workspace an eager call grew first: four replays over two inputs, with
+    eager work and synchronisations between them, each equal to the oracle."""
+    import torch
+    import paper_1312_0138_amd as bs
+    ka = inputs.distinct_uniform(n, rb, 23)
+    kb = inputs.distinct_uniform(n, rb, 24)
+    vals = np.random.default_rng(25).integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    wants = [o.bitwise_sort1_pairs(ka, vals, rb), o.bitwise_sort1_pairs(kb, vals, rb)]
+    k, v = to_dev(ka), to_dev(vals)
+    ok, ov = torch.empty_like(k), torch.empty_like(v)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bs.sort_pairs(k, v, rb, out_keys=ok, out_values=ov, stream=s)  # warm-up outside the capture
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
+        bs.sort_pairs(k, v, rb, out_keys=ok, out_values=ov, stream=s)
+    for rep in range(4):
+        k.copy_(to_dev(ka if rep % 2 == 0 else kb))
+        ok.fill_(-1)
+        scratch = torch.arange(1 << 20, device="cuda", dtype=torch.int32).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(scratch) >= 0
+        want_k, want_v = wants[rep % 2]
+        np.testing.assert_array_equal(to_np(ok), want_k, err_msg=f"replay {rep}")
+        np.testing.assert_array_equal(to_np(ov), want_v, err_msg=f"replay {rep}")
+        st = bs.status(s)
+        assert st.flags == 0 and st.count == n
